@@ -1,0 +1,154 @@
+"""ctypes wrapper and build step for the plain CPU oracle (test infrastructure only).
+
+Every function here forwards to `cjt_oracle.c`; see that file's header for what
+is computed and which passage of the paper each step follows.  `quad=True`
+selects the binary128 build of the same source (unmodified recurrence at every
+point, roughly 50x slower), used to check the long double build.
+"""
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cjt_oracle.c")
+_LIBS = {False: os.path.join(_HERE, "libcjt_oracle.so"), True: os.path.join(_HERE, "libcjt_oracle_q.so")}
+_lock = threading.Lock()
+_libs = {}
+
+
+def _build_one(quad):
+    out = _LIBS[quad]
+    cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-pthread"]
+    if quad:
+        cmd += ["-DORACLE_QUAD"]
+    cmd += [_SRC, "-o", out + ".tmp"]
+    cmd += ["-lquadmath", "-lm"] if quad else ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def build(force=True):
+    """Compile the oracle with gcc (round-to-nearest, no contraction, no
+    fast-math): the long double library and its binary128 cross-check build."""
+    for quad in (False, True):
+        lib = _LIBS[quad]
+        if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+            _build_one(quad)
+    return _LIBS[False]
+
+
+def _load(quad=False):
+    with _lock:
+        if quad in _libs:
+            return _libs[quad]
+        path = _LIBS[quad]
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            _build_one(quad)
+        lib = ctypes.CDLL(path)
+        i64, dbl, pd, pl = ctypes.c_int64, ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)
+        ci = ctypes.c_int
+        lib.oracle_forward.argtypes = [i64, dbl, dbl, pd, pd, ci]
+        lib.oracle_inverse.argtypes = [i64, dbl, dbl, pd, pd, ci]
+        lib.oracle_point_values.argtypes = [i64, dbl, dbl, pd, pd, ci]
+        lib.oracle_point_values_rows.argtypes = [i64, dbl, dbl, pd, i64, pl, pd, ci]
+        lib.oracle_jacobi_column.argtypes = [i64, dbl, dbl, i64, i64, pd]
+        lib.oracle_moments.argtypes = [i64, dbl, dbl, pd]
+        lib.oracle_cc_weights.argtypes = [i64, dbl, dbl, pd, ci]
+        lib.oracle_norm_consts.argtypes = [i64, dbl, dbl, pd]
+        for f in ("oracle_forward", "oracle_inverse", "oracle_point_values", "oracle_point_values_rows",
+                  "oracle_jacobi_column", "oracle_moments", "oracle_cc_weights", "oracle_norm_consts",
+                  "oracle_version"):
+            getattr(lib, f).restype = ctypes.c_int
+        _libs[quad] = lib
+        return lib
+
+
+def default_threads():
+    try:
+        return max(1, min(len(os.sched_getaffinity(0)), 64))
+    except AttributeError:
+        return max(1, os.cpu_count() or 1)
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check(st, what):
+    if st != 0:
+        raise RuntimeError(f"oracle {what} failed with status {st}")
+
+
+def forward(c, alpha, beta, threads=None, quad=False):
+    """Chebyshev coefficients T_N^{-1} P_N c of the Jacobi series c (length N+1)."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    N = c.size - 1
+    out = np.empty(N + 1)
+    _check(_load(quad).oracle_forward(N, float(alpha), float(beta), _dp(c), _dp(out), threads or default_threads()), "forward")
+    return out
+
+
+def inverse(cheb, alpha, beta, threads=None, quad=False):
+    """Jacobi coefficients P_N^{-1} T_N c of the Chebyshev series c (length N+1)."""
+    cheb = np.ascontiguousarray(cheb, dtype=np.float64)
+    N = cheb.size - 1
+    out = np.empty(N + 1)
+    _check(_load(quad).oracle_inverse(N, float(alpha), float(beta), _dp(cheb), _dp(out), threads or default_threads()), "inverse")
+    return out
+
+
+def point_values(c, alpha, beta, threads=None, quad=False):
+    """p_j = sum_n c_n P_n(cos(pi j/N)), j = 0..N."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    N = c.size - 1
+    out = np.empty(N + 1)
+    _check(_load(quad).oracle_point_values(N, float(alpha), float(beta), _dp(c), _dp(out), threads or default_threads()), "point_values")
+    return out
+
+
+def point_values_rows(c, alpha, beta, rows, threads=None, quad=False):
+    """p_j for the listed rows j only (O(N) per row)."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    N = c.size - 1
+    out = np.empty(rows.size)
+    _check(_load(quad).oracle_point_values_rows(N, float(alpha), float(beta), _dp(c), rows.size,
+                                            rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(out),
+                                            threads or default_threads()), "point_values_rows")
+    return out
+
+
+def jacobi_column(nmax, alpha, beta, j, d, quad=False):
+    """P_n(cos(pi j/d)) for n = 0..nmax."""
+    out = np.empty(nmax + 1)
+    _check(_load(quad).oracle_jacobi_column(nmax, float(alpha), float(beta), j, d, _dp(out)), "jacobi_column")
+    return out
+
+
+def moments(nmax, alpha, beta, quad=False):
+    """Modified Chebyshev moments of the Jacobi weight, n = 0..nmax."""
+    out = np.empty(nmax + 1)
+    _check(_load(quad).oracle_moments(nmax, float(alpha), float(beta), _dp(out)), "moments")
+    return out
+
+
+def cc_weights(L, alpha, beta, threads=None, quad=False):
+    """Clenshaw--Curtis weights of the Jacobi weight at cos(pi j/L), j = 0..L."""
+    out = np.empty(L + 1)
+    _check(_load(quad).oracle_cc_weights(L, float(alpha), float(beta), _dp(out), threads or default_threads()), "cc_weights")
+    return out
+
+
+def norm_consts(nmax, alpha, beta, quad=False):
+    """Orthonormality constants A_n = int P_n^2 w, n = 0..nmax."""
+    out = np.empty(nmax + 1)
+    _check(_load(quad).oracle_norm_consts(nmax, float(alpha), float(beta), _dp(out)), "norm_consts")
+    return out
+
+
+def version():
+    return int(_load(False).oracle_version())
