@@ -1,0 +1,147 @@
+/*
+ * cjt.h -- C-ABI of the MI355X Chebyshev--Jacobi transform library (libcjt_hip.so).
+ *
+ * The transform pair (Slevinsky, "On the use of Hahn's asymptotic formula and
+ * stabilized recurrence for a fast, simple, and stable Chebyshev--Jacobi
+ * transform", IMA J. Numer. Anal.):
+ *
+ *   forward   c_cheb = T_N^{-1} P_N c_jac        (Sec. 1, eq. CJT)
+ *   inverse   c_jac  = P_N^{-1} T_N c_cheb       (Sec. 1, eq. iCJT; computed by the
+ *                                                 transposed formula, Sec. 3, eq. CJTT)
+ *
+ * where [P_N]_{j,n} = P_n^{(alpha,beta)}(x_j), [T_N]_{j,k} = T_k(x_j) and
+ * x_j = cos(pi j / N), j = 0..N.  Both vectors hold N+1 doubles, index n (or k)
+ * at offset n.
+ *
+ * The plan/execute split follows Sec. 4 (FFTW-like): cjt_plan computes the
+ * partition of Sec. 2.2, the recurrence coefficients of Sec. 1.2 and 4.2, the
+ * Hahn diagonals of Sec. 2.1 and, for the inverse, the Clenshaw--Curtis
+ * weights and orthonormality constants of Sec. 3; execution applies them.
+ *
+ * Conventions for every entry point:
+ *   - Device pointers ("d_") are HIP device addresses on the device that is
+ *     current when the plan was created; host pointers are ordinary memory.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Execution calls are
+ *     asynchronous on that stream; argument errors are returned synchronously
+ *     and nothing is launched.  A stream is used by one call at a time: the
+ *     library keeps one workspace per stream.
+ *   - Plans are immutable after creation and may be used from several streams;
+ *     the caller owns every input and output buffer, the plan owns its device
+ *     arrays.  Out-of-place only: d_in == d_out returns CJT_EINVAL.
+ *   - On error, cjt_last_error() returns a message for the calling thread.
+ */
+#ifndef CJT_H
+#define CJT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cjt_plan_s* cjt_plan_t;
+
+typedef enum {
+    CJT_OK = 0,
+    CJT_EINVAL = 1,      /* bad size, pointer or flag */
+    CJT_EDOMAIN = 2,     /* alpha or beta outside (-1/2, 1/2] (Sec. 2.1), or M outside {0} U [2, 30] */
+    CJT_ENOMEM = 3,      /* device or host allocation failed */
+    CJT_EDEVICE = 4,     /* a HIP call failed */
+    CJT_EBUSY = 5,       /* resource in use */
+    CJT_EUNSUPPORTED = 6 /* valid request this build does not implement */
+} cjt_status;
+
+/* Plan flags. */
+enum {
+    CJT_FP64 = 0,          /* every step in FP64 */
+    CJT_FP32_BULK = 1      /* the DCT-I/DST-I of the Hahn blocks in FP32 with FP32 accumulation;
+                              diagonals, recurrences and boundary DCTs stay FP64 */
+};
+
+#define CJT_MAX_BLOCKS 16
+
+/* Partition of Sec. 2.2 for one grid: nblocks rectangles
+ * [win_lo[k], win_hi[k]] (grid indices, inclusive) x [deg_lo[k], deg_hi[k])
+ * (degrees, half-open) where Hahn's expansion with M terms is within eps;
+ * everything else is evaluated by recurrence. */
+typedef struct {
+    int64_t grid;            /* number of intervals G: points are cos(pi i / G), i = 0..G */
+    int32_t M;               /* terms used */
+    int32_t nblocks;         /* K' <= K */
+    int64_t n_M;             /* eq. for n_M, with the envelope g_M(pi/2) */
+    double alpha_N;          /* min(1/log(G/n_M), 1/2) */
+    int32_t K;               /* ceil(log(G/n_M)/log(1/alpha_N)) */
+    int32_t theta_bar;       /* grid index of the discrete minimiser of g_M */
+    int64_t deg_lo[CJT_MAX_BLOCKS], deg_hi[CJT_MAX_BLOCKS];
+    int64_t win_lo[CJT_MAX_BLOCKS], win_hi[CJT_MAX_BLOCKS];
+    int64_t rec_entries;     /* number of (point, degree) pairs left to recurrence */
+} cjt_partition_info;
+
+typedef struct {
+    int64_t N;
+    double alpha, beta;
+    int32_t M;               /* Hahn terms in use (chosen when 0 was requested) */
+    uint32_t flags;
+    double eps;              /* partition tolerance, 2^-52 */
+    cjt_partition_info fwd;  /* grid N, degrees 0..N */
+    cjt_partition_info inv;  /* grid 2N, degrees clipped to 0..N (Sec. 3.2) */
+    int64_t fft_len_fwd;     /* complex FFT length behind one DCT-I + DST-I pair: N */
+    int64_t fft_len_inv;     /* 2N */
+    int64_t fft_count_fwd;   /* Hahn-block transforms per forward call: M x nblocks */
+    int64_t fft_count_inv;
+    size_t device_bytes;     /* device memory held by the plan */
+} cjt_plan_info;
+
+/* Create a plan for degree N >= 1 (a power of two in this build; other N
+ * return CJT_EUNSUPPORTED), parameters (alpha, beta) in (-1/2, 1/2]
+ * (Sec. 2.1: Hahn's remainder bound), and M Hahn terms (0 = chosen by the
+ * library's cost model, else 2 <= M <= 30; Sec. 2.2 needs M >= 2).  flags is
+ * CJT_FP64 or CJT_FP32_BULK.  Plan arrays are computed on the device on
+ * `stream`; the call returns after they are complete.  *out receives the plan. */
+cjt_status cjt_plan(cjt_plan_t* out, int64_t N, double alpha, double beta, int M, unsigned flags,
+                    void* stream);
+
+/* Forward transform (eq. CJT): d_in = Jacobi coefficients c_0..c_N, d_out =
+ * Chebyshev coefficients, N+1 doubles each, device memory, no overlap. */
+cjt_status cjt_forward(cjt_plan_t plan, const double* d_in, double* d_out, void* stream);
+
+/* Inverse transform (eq. iCJT via eq. CJTT): d_in = Chebyshev coefficients,
+ * d_out = Jacobi coefficients, N+1 doubles each, device memory, no overlap. */
+cjt_status cjt_inverse(cjt_plan_t plan, const double* d_in, double* d_out, void* stream);
+
+/* Batched forward/inverse: `count` independent transforms, transform i uses
+ * plans[i] (a host array; plans may repeat) and the ragged slices
+ * d_in[offsets[i] .. offsets[i+1]) and d_out[same], where offsets is a host
+ * array of count+1 entries with offsets[i+1] - offsets[i] = N_i + 1.  All
+ * plans must share one precision flag.  One launch sequence serves the whole
+ * batch. */
+cjt_status cjt_forward_batched(const cjt_plan_t* plans, int64_t count, const int64_t* offsets,
+                               const double* d_in, double* d_out, void* stream);
+cjt_status cjt_inverse_batched(const cjt_plan_t* plans, int64_t count, const int64_t* offsets,
+                               const double* d_in, double* d_out, void* stream);
+
+/* Describe a plan (host memory out). */
+cjt_status cjt_plan_query(cjt_plan_t plan, cjt_plan_info* out);
+
+/* Host-only: the plan summary cjt_plan would build (partitions, chosen M,
+ * transform counts), without touching a device.  device_bytes is an estimate. */
+cjt_status cjt_plan_describe(int64_t N, double alpha, double beta, int M, unsigned flags, cjt_plan_info* out);
+
+/* Release a plan (waits for the device to finish with it). NULL is accepted. */
+cjt_status cjt_plan_destroy(cjt_plan_t plan);
+
+/* Static text for a status code. */
+const char* cjt_strerror(cjt_status status);
+
+/* Detail message of the last error on the calling thread ("" if none). */
+const char* cjt_last_error(void);
+
+/* Library version, as major*10000 + minor*100 + patch. */
+int cjt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CJT_H */

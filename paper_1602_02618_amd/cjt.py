@@ -1,0 +1,252 @@
+"""ctypes binding of libcjt_hip.so (C-ABI in include/cjt.h), same names.
+
+Argument marshalling only: every step of the transform runs in the HIP
+library.  Device buffers are passed as torch tensors (float64, contiguous, on
+the GPU) or as raw integer device addresses; streams as torch.cuda.Stream,
+raw hipStream_t integers, or None for torch's current stream.
+
+The library must have been built (`python -m paper_1602_02618_amd.build`);
+there is no fallback: if it is missing, loading raises.
+"""
+import ctypes
+import os
+import threading
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcjt_hip.so")
+
+CJT_OK, CJT_EINVAL, CJT_EDOMAIN, CJT_ENOMEM, CJT_EDEVICE, CJT_EBUSY, CJT_EUNSUPPORTED = range(7)
+CJT_FP64 = 0
+CJT_FP32_BULK = 1
+CJT_MAX_BLOCKS = 16
+
+_EXPORTS = (
+    "cjt_plan", "cjt_forward", "cjt_inverse", "cjt_forward_batched", "cjt_inverse_batched",
+    "cjt_plan_query", "cjt_plan_describe", "cjt_plan_destroy", "cjt_strerror", "cjt_last_error",
+    "cjt_version",
+)
+
+
+class cjt_partition_info(ctypes.Structure):
+    _fields_ = [
+        ("grid", ctypes.c_int64),
+        ("M", ctypes.c_int32),
+        ("nblocks", ctypes.c_int32),
+        ("n_M", ctypes.c_int64),
+        ("alpha_N", ctypes.c_double),
+        ("K", ctypes.c_int32),
+        ("theta_bar", ctypes.c_int32),
+        ("deg_lo", ctypes.c_int64 * CJT_MAX_BLOCKS),
+        ("deg_hi", ctypes.c_int64 * CJT_MAX_BLOCKS),
+        ("win_lo", ctypes.c_int64 * CJT_MAX_BLOCKS),
+        ("win_hi", ctypes.c_int64 * CJT_MAX_BLOCKS),
+        ("rec_entries", ctypes.c_int64),
+    ]
+
+    def blocks(self):
+        """[(deg_lo, deg_hi, win_lo, win_hi), ...] for the nblocks Hahn blocks."""
+        return [(self.deg_lo[k], self.deg_hi[k], self.win_lo[k], self.win_hi[k]) for k in range(self.nblocks)]
+
+
+class cjt_plan_info(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64),
+        ("alpha", ctypes.c_double),
+        ("beta", ctypes.c_double),
+        ("M", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("eps", ctypes.c_double),
+        ("fwd", cjt_partition_info),
+        ("inv", cjt_partition_info),
+        ("fft_len_fwd", ctypes.c_int64),
+        ("fft_len_inv", ctypes.c_int64),
+        ("fft_count_fwd", ctypes.c_int64),
+        ("fft_count_inv", ctypes.c_int64),
+        ("device_bytes", ctypes.c_size_t),
+    ]
+
+
+class CJTError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__(f"{what}: {_strerror(status)} ({status}): {_last_error()}")
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Open libcjt_hip.so (once) and declare its signatures."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RuntimeError(f"HIP library {path} is not built; run `python -m paper_1602_02618_amd.build`")
+        lib = ctypes.CDLL(path)
+        vp, i64, dbl, ci, cu = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int, ctypes.c_uint
+        P = ctypes.POINTER
+        lib.cjt_plan.argtypes = [P(vp), i64, dbl, dbl, ci, cu, vp]
+        lib.cjt_forward.argtypes = [vp, vp, vp, vp]
+        lib.cjt_inverse.argtypes = [vp, vp, vp, vp]
+        lib.cjt_forward_batched.argtypes = [P(vp), i64, P(i64), vp, vp, vp]
+        lib.cjt_inverse_batched.argtypes = [P(vp), i64, P(i64), vp, vp, vp]
+        lib.cjt_plan_query.argtypes = [vp, P(cjt_plan_info)]
+        lib.cjt_plan_describe.argtypes = [i64, dbl, dbl, ci, cu, P(cjt_plan_info)]
+        lib.cjt_plan_destroy.argtypes = [vp]
+        lib.cjt_strerror.argtypes = [ci]
+        lib.cjt_strerror.restype = ctypes.c_char_p
+        lib.cjt_last_error.argtypes = []
+        lib.cjt_last_error.restype = ctypes.c_char_p
+        lib.cjt_version.argtypes = []
+        lib.cjt_version.restype = ci
+        for f in ("cjt_plan", "cjt_forward", "cjt_inverse", "cjt_forward_batched", "cjt_inverse_batched",
+                  "cjt_plan_query", "cjt_plan_describe", "cjt_plan_destroy"):
+            getattr(lib, f).restype = ci
+        _lib = lib
+        return lib
+
+
+def _strerror(st):
+    return load().cjt_strerror(int(st)).decode()
+
+
+def _last_error():
+    return load().cjt_last_error().decode()
+
+
+def _check(st, what):
+    if st != CJT_OK:
+        raise CJTError(st, what)
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    # torch tensor on the GPU, float64, contiguous
+    if getattr(x, "dtype", None) is not None:
+        import torch
+        if x.dtype != torch.float64 or not x.is_contiguous() or not x.is_cuda:
+            raise ValueError("device buffers must be contiguous float64 GPU tensors")
+        return x.data_ptr()
+    raise TypeError(f"cannot pass {type(x)!r} as a device pointer")
+
+
+def _stream(s):
+    if s is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except ImportError:
+            pass
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+class Plan:
+    """Owning wrapper of a cjt_plan_t."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def destroy(self):
+        if self.handle:
+            h, self.handle = self.handle, None
+            load().cjt_plan_destroy(h)
+
+    @property
+    def info(self):
+        return cjt_plan_query(self)
+
+    @property
+    def N(self):
+        return self.info.N
+
+
+def cjt_plan(N, alpha, beta, M=0, flags=CJT_FP64, stream=None):
+    h = ctypes.c_void_p()
+    _check(load().cjt_plan(ctypes.byref(h), int(N), float(alpha), float(beta), int(M), int(flags), _stream(stream)),
+           "cjt_plan")
+    return Plan(h.value)
+
+
+def cjt_forward(plan, d_in, d_out, stream=None):
+    _check(load().cjt_forward(plan.handle, _ptr(d_in), _ptr(d_out), _stream(stream)), "cjt_forward")
+
+
+def cjt_inverse(plan, d_in, d_out, stream=None):
+    _check(load().cjt_inverse(plan.handle, _ptr(d_in), _ptr(d_out), _stream(stream)), "cjt_inverse")
+
+
+def _batched(fn, what, plans, offsets, d_in, d_out, stream):
+    n = len(plans)
+    arr = (ctypes.c_void_p * max(n, 1))(*[p.handle for p in plans])
+    offs = (ctypes.c_int64 * (n + 1))(*[int(o) for o in offsets])
+    _check(fn(arr, n, offs, _ptr(d_in), _ptr(d_out), _stream(stream)), what)
+
+
+def cjt_forward_batched(plans, offsets, d_in, d_out, stream=None):
+    _batched(load().cjt_forward_batched, "cjt_forward_batched", plans, offsets, d_in, d_out, stream)
+
+
+def cjt_inverse_batched(plans, offsets, d_in, d_out, stream=None):
+    _batched(load().cjt_inverse_batched, "cjt_inverse_batched", plans, offsets, d_in, d_out, stream)
+
+
+def cjt_plan_query(plan):
+    info = cjt_plan_info()
+    _check(load().cjt_plan_query(plan.handle, ctypes.byref(info)), "cjt_plan_query")
+    return info
+
+
+def cjt_plan_describe(N, alpha, beta, M=0, flags=CJT_FP64):
+    info = cjt_plan_info()
+    _check(load().cjt_plan_describe(int(N), float(alpha), float(beta), int(M), int(flags), ctypes.byref(info)),
+           "cjt_plan_describe")
+    return info
+
+
+def cjt_plan_destroy(plan):
+    plan.destroy()
+
+
+def cjt_strerror(status):
+    return _strerror(status)
+
+
+def cjt_last_error():
+    return _last_error()
+
+
+def cjt_version():
+    return int(load().cjt_version())
+
+
+# ---------------------------------------------------------------- conveniences
+
+def forward(plan, x, stream=None):
+    """Allocate and return the forward transform of the GPU tensor x."""
+    import torch
+    out = torch.empty_like(x)
+    cjt_forward(plan, x, out, stream)
+    return out
+
+
+def inverse(plan, x, stream=None):
+    """Allocate and return the inverse transform of the GPU tensor x."""
+    import torch
+    out = torch.empty_like(x)
+    cjt_inverse(plan, x, out, stream)
+    return out

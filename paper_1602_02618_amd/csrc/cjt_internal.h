@@ -1,0 +1,104 @@
+// Internal types shared by the HIP sources of libcjt_hip.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/cjt.h"
+
+namespace cjt {
+
+constexpr int kMaxBlocks = CJT_MAX_BLOCKS;
+constexpr int kMaxM = 30;
+
+// Complex value in registers / LDS / global memory.
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+    T re, im;
+};
+
+// A group of grid points handled by one recurrence work-item: points
+// p0 .. p0+np-1, all with the same recurrence form (mode 0 = three-term
+// recurrence, +1 / -1 = the modified form anchored at x0 = +1 / -1) and the same
+// number of degrees `cut` left to recurrence.  `off` is the offset of this
+// task's partial sums (inverse direction only).
+struct RecTask {
+    int32_t p0;
+    int32_t np;
+    int32_t mode;
+    int32_t cut;
+    int64_t off;
+};
+
+// Everything one kernel needs to know about one transform of a launch.  Built
+// on the host for every call and copied to the device as an array.
+struct ExecDesc {
+    int64_t N;          // degree
+    int64_t G;          // grid intervals: N (forward) or 2N (inverse)
+    double alpha, beta;
+    int32_t M;          // Hahn terms
+    int32_t nblk;       // Hahn blocks
+    int32_t ntasks;     // recurrence tasks
+    int32_t pad0;
+    int64_t deg_lo[kMaxBlocks], deg_hi[kMaxBlocks];  // half-open degree ranges of the blocks
+    int64_t win_lo[kMaxBlocks], win_hi[kMaxBlocks];  // inclusive grid windows of the blocks
+    const double* C;          // [M][N+1]   Hahn coefficients C_{n,m}
+    const cx<double>* uv;     // [M][G+1]   (u_m, v_m) at the grid points
+    const double* w;          // [2N+1]     Clenshaw--Curtis weights (inverse)
+    const double* s;          // [N+1]      1 / A_n (inverse)
+    const RecTask* tasks;     // [ntasks]   recurrence tasks, longest first
+    const double4* rec0;      // [N+2]      three-term coefficients
+    const double4* recp;      // [N+2]      modified form at x0 = +1
+    const double4* recm;      // [N+2]      modified form at x0 = -1
+    const double* in;         // input coefficients (N+1)
+    double* out;              // output coefficients (N+1)
+    double* p;                // forward: point values (N+1); inverse: g = w .* f (2N+1)
+    double* part;             // inverse: recurrence partial sums
+    void* tmp;                // FFT intermediates [nblk*M][L] complex
+};
+
+// Geometry of one complex FFT length L (a power of two) on the device.
+struct FftGeom {
+    int64_t L;        // complex length
+    int32_t logL;
+    int32_t single;   // 1: whole transform in one workgroup (L <= kSingleMax)
+    int32_t L1, L2;   // two-pass split, L = L1 * L2 (column pass over L1, row pass over L2)
+    int32_t logL1, logL2;
+    const void* tw;   // [2L] e^{i pi q / L}, in the precision of the transform
+};
+
+constexpr int64_t kSingleMax = 4096;
+
+// Error reporting (thread-local detail message).
+void set_error(const std::string& msg);
+cjt_status fail(cjt_status st, const std::string& msg);
+
+#define CJT_HIP_TRY(expr)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::cjt::fail(CJT_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Launchers implemented in the .hip files.
+struct EngineArgs {
+    const ExecDesc* d_desc;   // device array of descriptors
+    int count;                // instances in the launch
+    int max_jobs;             // max nblk*M over the instances
+    int max_tasks;            // max ntasks over the instances
+    FftGeom geom;             // all instances of one launch share L
+    hipStream_t stream;
+};
+
+enum class Src { FwdAsy, InvAsy, FwdFinal, InvInit, Moments };
+enum class Sink { FwdAsy, InvAsy, FwdFinal, InvInit, Weights };
+
+cjt_status launch_rdft(const EngineArgs& a, Src src, Sink sink, bool fp32);
+cjt_status launch_rec_fwd(const EngineArgs& a);
+cjt_status launch_rec_inv(const EngineArgs& a);
+cjt_status launch_rec_inv_reduce(const EngineArgs& a, int64_t maxN);
+cjt_status make_twiddles(int64_t L, bool fp32, const void** out, hipStream_t stream);
+
+}  // namespace cjt

@@ -1,0 +1,207 @@
+// LDS-resident Stockham FFTs for gfx950 (wave64), positive exponent:
+//   X_k = sum_n x_n exp(+2 pi i n k / F),  F = 2^p.
+//
+// A transform is split into radix-16 stages (plus one radix-8/4/2 stage when
+// p is not a multiple of 4).  Every thread holds 16 complex values per stage
+// in registers: one radix-16 butterfly, or 16/R radix-R butterflies.  Each stage
+// reads its inputs from LDS, waits at a barrier, and writes its outputs in
+// Stockham order, so the result comes out in natural order without a
+// bit-reversal pass.  LDS indices are padded by one element every 16 so the
+// stride-16 writes of the first stage do not serialise on one bank.
+//
+// Twiddles come from a table tw[q] = exp(i pi q / L), q < 2L, of the transform
+// length L that this F-point transform is part of (F divides L); they are
+// computed once per length from the exact rational angle, so no angle is ever
+// formed by accumulation.
+#pragma once
+
+#include "cjt_internal.h"
+
+namespace cjt {
+
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b)
+{
+    return {fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cmul_i(cx<T> a) { return {-a.im, a.re}; }      // i * a
+template <typename T>
+__device__ __forceinline__ cx<T> cmul_mi(cx<T> a) { return {a.im, -a.re}; }     // -i * a
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+
+// In-register DFTs, positive exponent.
+template <typename T>
+__device__ __forceinline__ void dft2(cx<T>* v)
+{
+    cx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(cx<T>& v0, cx<T>& v1, cx<T>& v2, cx<T>& v3)
+{
+    cx<T> t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3), t3 = csub(v1, v3);
+    v0 = cadd(t0, t2);
+    v2 = csub(t0, t2);
+    v1 = cadd(t1, cmul_i(t3));
+    v3 = csub(t1, cmul_i(t3));
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(cx<T>* v) { dft4(v[0], v[1], v[2], v[3]); }
+
+template <typename T>
+__device__ __forceinline__ void dft8(cx<T>* v)
+{
+    const T h = (T)0.70710678118654752440084436210484903928;
+    cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    cx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    // w8^k o_k, w8 = e^{i pi/4}
+    cx<T> w1 = {h * (o1.re - o1.im), h * (o1.re + o1.im)};
+    cx<T> w2 = cmul_i(o2);
+    cx<T> w3 = {-h * (o3.re + o3.im), h * (o3.re - o3.im)};
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, w1);
+    v[5] = csub(e1, w1);
+    v[2] = cadd(e2, w2);
+    v[6] = csub(e2, w2);
+    v[3] = cadd(e3, w3);
+    v[7] = csub(e3, w3);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft16(cx<T>* v)
+{
+    const T c1 = (T)0.92387953251128675612818318939678828682;  // cos(pi/8)
+    const T s1 = (T)0.38268343236508977172845998403039886676;  // sin(pi/8)
+    const T h = (T)0.70710678118654752440084436210484903928;
+    // n = q + 4p: DFT over p for each q
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dft4(v[q], v[q + 4], v[q + 8], v[q + 12]);
+    // now v[q + 4 k1] = A_q[k1]; twiddle by w16^{q k1}
+    // q = 1: k1 = 1,2,3 -> w^1, w^2, w^3
+    v[5] = cmul(v[5], cx<T>{c1, s1});
+    v[9] = cmul(v[9], cx<T>{h, h});
+    v[13] = cmul(v[13], cx<T>{s1, c1});
+    // q = 2: w^2, w^4, w^6
+    v[6] = cmul(v[6], cx<T>{h, h});
+    v[10] = cmul_i(v[10]);
+    v[14] = cmul(v[14], cx<T>{-h, h});
+    // q = 3: w^3, w^6, w^9
+    v[7] = cmul(v[7], cx<T>{s1, c1});
+    v[11] = cmul(v[11], cx<T>{-h, h});
+    v[15] = cmul(v[15], cx<T>{-c1, -s1});
+    // DFT over q for each k1: X[k1 + 4 k2]
+    cx<T> o[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        cx<T> a0 = v[4 * k1 + 0], a1 = v[4 * k1 + 1], a2 = v[4 * k1 + 2], a3 = v[4 * k1 + 3];
+        dft4(a0, a1, a2, a3);
+        o[k1] = a0;
+        o[k1 + 4] = a1;
+        o[k1 + 8] = a2;
+        o[k1 + 12] = a3;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = o[i];
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft(cx<T>* v)
+{
+    if constexpr (R == 2) dft2(v);
+    else if constexpr (R == 4) dft4(v);
+    else if constexpr (R == 8) dft8(v);
+    else dft16(v);
+}
+
+// One Stockham stage of radix R for an F-point transform at buf[base .. base+F)
+// (padded indices).  `lt` is the thread's index among the F/16 threads that
+// serve this transform (or 0 when F < 16), BPT = butterflies per thread.
+// twmul = 2L / (Ns R) maps the stage twiddle exp(2 pi i r k / (Ns R)) into tw.
+template <typename T, int R, int BPT>
+__device__ __forceinline__ void fft_stage(cx<T>* buf, int F, int Ns, int lt, int base, bool active,
+                                          const cx<T>* __restrict__ tw, int64_t twmul)
+{
+    cx<T> v[BPT][R];
+    const int FR = F / R;
+    const int stride = FR / BPT;  // threads per transform
+    if (active) {
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            int j = lt + q * stride;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = buf[lds_pad(base + j + r * FR)];
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            int j = lt + q * stride;
+            int k = j & (Ns - 1);
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[(int64_t)(r * k) * twmul]);
+            }
+            dft<T, R>(v[q]);
+            int idxD = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[lds_pad(base + idxD + r * Ns)] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+// nfft transforms of size F = 2^logF stored back to back from buf[0] (padded
+// indices), using threads [0, nfft * max(F/16, 1)) of the workgroup.  All
+// threads of the workgroup must call this.  L2x = 2L of the parent length.
+template <typename T>
+__device__ __forceinline__ void lds_fft(cx<T>* buf, int logF, int nfft, const cx<T>* __restrict__ tw,
+                                        int64_t L2x)
+{
+    const int F = 1 << logF;
+    if (logF == 0) {
+        __syncthreads();
+        return;
+    }
+    const int tpf = F >= 16 ? F / 16 : 1;
+    const int tid = threadIdx.x;
+    const int b = tid / tpf;
+    const int lt = tid - b * tpf;
+    const bool active = b < nfft;
+    const int base = b * F;
+    int Ns = 1;
+    int rem = logF;
+    while (rem > 0) {
+        const int lr = rem >= 4 ? 4 : rem;
+        const int64_t twmul = L2x / ((int64_t)Ns << lr);
+        if (lr == 4) {
+            fft_stage<T, 16, 1>(buf, F, Ns, lt, base, active, tw, twmul);
+        } else if (F >= 16) {
+            if (lr == 3) fft_stage<T, 8, 2>(buf, F, Ns, lt, base, active, tw, twmul);
+            else if (lr == 2) fft_stage<T, 4, 4>(buf, F, Ns, lt, base, active, tw, twmul);
+            else fft_stage<T, 2, 8>(buf, F, Ns, lt, base, active, tw, twmul);
+        } else {
+            if (lr == 3) fft_stage<T, 8, 1>(buf, F, Ns, lt, base, active, tw, twmul);
+            else if (lr == 2) fft_stage<T, 4, 1>(buf, F, Ns, lt, base, active, tw, twmul);
+            else fft_stage<T, 2, 1>(buf, F, Ns, lt, base, active, tw, twmul);
+        }
+        Ns <<= lr;
+        rem -= lr;
+    }
+}
+
+}  // namespace cjt

@@ -1,0 +1,58 @@
+// Plan object and host-side planning helpers.
+#pragma once
+
+#include <vector>
+
+#include "cjt_internal.h"
+
+namespace cjt {
+
+// Partition of one grid (Sec. 2.2).  Blocks are rectangles
+// [win_lo, win_hi] x [deg_lo, deg_hi) in (grid index, degree).
+struct Part {
+    int64_t G = 0;        // grid intervals
+    int64_t cap = 0;      // highest degree
+    int M = 0;            // Hahn terms used
+    int64_t n_M = 0;
+    double alpha_N = 0.0;
+    int K = 0;
+    int64_t theta_bar = 0;
+    int nblk = 0;
+    int exact = 0;        // expansion exact with one term (alpha = beta = 1/2)
+    int64_t deg_lo[kMaxBlocks] = {}, deg_hi[kMaxBlocks] = {};
+    int64_t win_lo[kMaxBlocks] = {}, win_hi[kMaxBlocks] = {};
+    int64_t rec_entries = 0;
+};
+
+struct Plan {
+    int64_t N = 0;
+    double alpha = 0.0, beta = 0.0;
+    unsigned flags = 0;
+    int device = 0;
+    Part fwd, inv;
+    std::vector<RecTask> tasks_f, tasks_i;
+    int64_t part_total_f = 0, part_total_i = 0;
+    // device arena and its views
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    double* C = nullptr;
+    cx<double>* uv_f = nullptr;
+    cx<double>* uv_i = nullptr;
+    double* w = nullptr;
+    double* s = nullptr;
+    double4 *f0 = nullptr, *fp = nullptr, *fm = nullptr;
+    double4 *i0 = nullptr, *ip = nullptr, *im = nullptr;
+    RecTask* d_tasks_f = nullptr;
+    RecTask* d_tasks_i = nullptr;
+};
+
+constexpr int kRecWidthFwd = 64;        // points per forward recurrence task (one per lane)
+constexpr int kRecWidthInv = 64 * 4;    // points per inverse task (4 per lane)
+
+void compute_partition(int64_t G, int64_t cap, double a, double b, int M, Part* P);
+void choose_partitions(int64_t N, double a, double b, int M, Part* f, Part* inv);
+void build_tasks(const Part& P, int width, std::vector<RecTask>* out, int64_t* part_total);
+cjt_status build_plan_device(Plan* P, hipStream_t st);
+cjt_status fft_geometry(int64_t L, bool fp32, hipStream_t st, FftGeom* g);
+
+}  // namespace cjt

@@ -1,0 +1,536 @@
+// Plan construction (Sec. 4, "Planification"): partition, recurrence
+// coefficients, Hahn diagonals, Clenshaw--Curtis weights, orthonormality
+// constants and recurrence work lists.  The partition and work lists are
+// host-side integer bookkeeping over O(log N) window edges; every per-degree
+// and per-point array is computed by a device kernel in FP64.
+#include <math.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "cjt_internal.h"
+#include "plan.h"
+#include "planmath.h"
+
+namespace cjt {
+
+// ------------------------------------------------------------------ partition (Sec. 2.2)
+
+namespace {
+
+// log g_M(theta_i), theta_i = pi i / G: the envelope of |f_M| (Sec. 2.2),
+// summed in log space; -inf when every coefficient vanishes (a = b = 1/2).
+double log_gM(double th2, int M, const double* ca, const double* cb, double a, double b)
+{
+    const double ls = log(sin(th2)), lc = log(cos(th2));
+    double t[kMaxM + 2];
+    int nt = 0;
+    double mx = -INFINITY;
+    for (int l = 0; l <= M; ++l) {
+        const double coef = ca[l] * cb[M - l];
+        if (!(coef > 0.0)) continue;
+        t[nt] = log(coef) + (l - M - b - 0.5) * lc - (l + a + 0.5) * ls;
+        mx = fmax(mx, t[nt]);
+        ++nt;
+    }
+    if (nt == 0) return -INFINITY;
+    double s = 0.0;
+    for (int q = 0; q < nt; ++q) s += exp(t[q] - mx);
+    return mx + log(s);
+}
+
+}  // namespace
+
+void compute_partition(int64_t G, int64_t cap, double a, double b, int M, Part* P)
+{
+    *P = Part{};
+    P->G = G;
+    P->cap = cap;
+    P->M = M;
+    double ca[kMaxM + 2], cb[kMaxM + 2];
+    hahn_pochhammer(M, a, b, ca, cb);
+    auto lg = [&](int64_t i) { return log_gM(kPi * (double)i / (2.0 * (double)G), M, ca, cb, a, b); };
+    const double leps = log(kEps);
+    const double lg_half = log_gM(kPi / 4.0, M, ca, cb, a, b);  // g_M(pi/2)
+    const int64_t ncap1 = cap + 1;
+    P->rec_entries = (G + 1) * ncap1;
+    if (lg_half == -INFINITY) {
+        // f_m = 0 for m >= 1: Hahn's expansion with one term is exact (a = b = 1/2).
+        P->exact = 1;
+        P->M = 1;
+        P->n_M = 1;
+        P->alpha_N = 0.5;
+        P->K = 1;
+        P->theta_bar = G / 2;
+        if (G >= 2 && cap >= 2) {
+            P->nblk = 1;
+            P->deg_lo[0] = 2;
+            P->deg_hi[0] = ncap1;
+            P->win_lo[0] = 1;
+            P->win_hi[0] = G - 1;
+            P->rec_entries -= (G - 1) * (ncap1 - 2);
+        }
+        return;
+    }
+    // n_M = floor((eps 2^(2M-1) sqrt(pi) / g_M(pi/2))^(-1/(M+1/2)))
+    const double lnM = -(leps + (2.0 * M - 1.0) * log(2.0) + 0.5 * log(kPi) - lg_half) / (M + 0.5);
+    P->n_M = lnM > 60.0 ? ((int64_t)1 << 60) : (int64_t)floor(exp(lnM));
+    if (P->n_M < 1) P->n_M = 1;
+    if (G < 3 || G <= P->n_M) return;
+    P->alpha_N = fmin(1.0 / log((double)G / (double)P->n_M), 0.5);
+    P->K = (int)ceil(log((double)G / (double)P->n_M) / log(1.0 / P->alpha_N));
+    // discrete minimiser of g_M over i = 1..G-1 (g_M is convex on (0, pi):
+    // each term is a positive multiple of sin^-p(theta/2) cos^-q(theta/2), p, q > 0)
+    int64_t lo = 1, hi = G - 1;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (lg(mid + 1) >= lg(mid)) hi = mid;
+        else lo = mid + 1;
+    }
+    const int64_t tb = lo;
+    P->theta_bar = tb;
+    const double lgb = lg(tb);
+    int64_t prev_cut = ncap1;
+    for (int k = 1; k <= kMaxBlocks; ++k) {
+        const int64_t jk = (int64_t)floor(pow(P->alpha_N, k) * (double)G);
+        if (jk <= P->n_M || jk < 2) break;
+        const double l2c = log(2.0) + hahn_logC((double)jk, P->M, a, b);
+        if (!(l2c + lgb < leps)) break;
+        // contiguous window around theta_bar where 2 C_{jk,M} g_M < eps
+        int64_t L = 1, R = tb;
+        while (L < R) {
+            const int64_t mid = L + (R - L) / 2;
+            if (l2c + lg(mid) < leps) R = mid;
+            else L = mid + 1;
+        }
+        const int64_t wlo = L;
+        L = tb;
+        R = G - 1;
+        while (L < R) {
+            const int64_t mid = L + (R - L + 1) / 2;
+            if (l2c + lg(mid) < leps) L = mid;
+            else R = mid - 1;
+        }
+        const int64_t whi = L;
+        const int64_t dlo = std::min(jk, ncap1);
+        const int64_t dhi = prev_cut;
+        if (dlo < dhi) {
+            const int q = P->nblk++;
+            P->deg_lo[q] = dlo;
+            P->deg_hi[q] = dhi;
+            P->win_lo[q] = wlo;
+            P->win_hi[q] = whi;
+            P->rec_entries -= (whi - wlo + 1) * (dhi - dlo);
+        }
+        prev_cut = std::min(prev_cut, dlo);
+    }
+}
+
+// cut(i): degrees [0, cut) of grid point i left to recurrence.
+static int64_t point_cut(const Part& P, int64_t i)
+{
+    int64_t c = P.cap + 1;
+    for (int k = 0; k < P.nblk; ++k)
+        if (i >= P.win_lo[k] && i <= P.win_hi[k]) c = P.deg_lo[k];
+    return c;
+}
+
+// Switch rule (Sec. 4.2): modified recurrences for theta <= pi/4 and >= 3pi/4.
+static int point_mode(int64_t i, int64_t G)
+{
+    if (4 * i <= G) return +1;
+    if (4 * i >= 3 * G) return -1;
+    return 0;
+}
+
+void build_tasks(const Part& P, int width, std::vector<RecTask>* out, int64_t* part_total)
+{
+    const int64_t G = P.G;
+    std::vector<int64_t> bp = {0, G + 1, G / 4 + 1, (3 * G + 3) / 4};
+    for (int k = 0; k < P.nblk; ++k) {
+        bp.push_back(P.win_lo[k]);
+        bp.push_back(P.win_hi[k] + 1);
+    }
+    std::sort(bp.begin(), bp.end());
+    bp.erase(std::unique(bp.begin(), bp.end()), bp.end());
+    out->clear();
+    for (size_t s = 0; s + 1 < bp.size(); ++s) {
+        int64_t a = bp[s], e = bp[s + 1];
+        if (a < 0) a = 0;
+        if (e > G + 1) e = G + 1;
+        if (a >= e) continue;
+        const int64_t cut = point_cut(P, a);
+        const int mode = point_mode(a, G);
+        for (int64_t p = a; p < e; p += width) {
+            RecTask t;
+            t.p0 = (int32_t)p;
+            t.np = (int32_t)std::min<int64_t>(width, e - p);
+            t.mode = mode;
+            t.cut = (int32_t)cut;
+            t.off = 0;
+            out->push_back(t);
+        }
+    }
+    std::stable_sort(out->begin(), out->end(), [](const RecTask& x, const RecTask& y) { return x.cut > y.cut; });
+    int64_t off = 0;
+    for (auto& t : *out) {
+        t.off = off;
+        off += t.cut;
+    }
+    *part_total = off;
+}
+
+// ------------------------------------------------------------------ M selection
+
+// Predicted cost of one forward plus one inverse transform for a given M:
+// Hahn blocks cost one complex FFT of length L per (block, term) and the
+// recurrence a few FP64 operations per (point, degree) pair.
+static double plan_cost(int64_t N, const Part& f, const Part& i)
+{
+    auto fft = [](double L) { return 5.0 * L * log2(fmax(L, 2.0)); };
+    const double rec = 8.0;
+    return f.nblk * f.M * fft((double)N) + i.nblk * i.M * fft(2.0 * (double)N) +
+           rec * (double)(f.rec_entries + i.rec_entries);
+}
+
+void choose_partitions(int64_t N, double a, double b, int M, Part* f, Part* inv)
+{
+    if (M > 0) {
+        compute_partition(N, N, a, b, M, f);
+        compute_partition(2 * N, N, a, b, M, inv);
+        return;
+    }
+    double best = INFINITY;
+    for (int m = 5; m <= 20; ++m) {
+        Part pf, pi;
+        compute_partition(N, N, a, b, m, &pf);
+        compute_partition(2 * N, N, a, b, m, &pi);
+        const double c = plan_cost(N, pf, pi);
+        if (c < best) {
+            best = c;
+            *f = pf;
+            *inv = pi;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ device kernels
+
+// Recurrence coefficients (Sec. 1.2) and the endpoint ratios of Sec. 4.2.
+//   f0[n] = (A_n, B_n, C_{n+1})                    forward, three-term
+//   fp/fm[n] = (A_n, C_{n+1} rb_{n+1}, 1/rb_n)     forward, modified at x0 = +1 / -1
+//   i0[n] = (A_n, B_n, C_n)                        inverse, three-term
+//   ip/im[n] = (A_n, C_n / rf_{n-1}, rf_n)         inverse, modified at x0 = +1 / -1
+__device__ inline void rec_ABC(double n, double a, double b, double* A, double* B, double* C)
+{
+    if (n == 0.0) {
+        *A = 0.5 * (a + b + 2.0);
+        *B = 0.5 * (a - b);
+        *C = 0.0;
+        return;
+    }
+    const double s = 2.0 * n + a + b;
+    const double den = 2.0 * (n + 1.0) * (n + a + b + 1.0);
+    *A = (s + 1.0) * (s + 2.0) / den;
+    *B = (a - b) * (a + b) * (s + 1.0) / (den * s);
+    *C = (n + a) * (n + b) * (s + 2.0) / ((n + 1.0) * (n + a + b + 1.0) * s);
+}
+
+// r^b_n(+-1) of the lemma in Sec. 4.2, n >= 1.
+__device__ inline double rb_pm(double n, double a, double b, int side)
+{
+    const double r = (n + 1.0) / n * (a + b + n + 1.0) * (a + b + 2.0 * n) / ((a + b + 2.0 * n + 2.0));
+    return side > 0 ? r / (n + b) : -r / (n + a);
+}
+
+// r^f_n(+-1) = P_{n+1}(+-1) / P_n(+-1) (Sec. 4.2).
+__device__ inline double rf_pm(double n, double a, double b, int side)
+{
+    return side > 0 ? (n + a + 1.0) / (n + 1.0) : -(n + b + 1.0) / (n + 1.0);
+}
+
+__global__ void k_plan_rec(int64_t N, double a, double b, double4* f0, double4* fp, double4* fm, double4* i0,
+                           double4* ip, double4* im)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n > N) return;
+    const double dn = (double)n;
+    double A, B, C, A1, B1, C1;
+    rec_ABC(dn, a, b, &A, &B, &C);
+    rec_ABC(dn + 1.0, a, b, &A1, &B1, &C1);
+    f0[n] = make_double4(A, B, C1, 0.0);
+    i0[n] = make_double4(A, B, C, 0.0);
+    const double rbp1 = rb_pm(dn + 1.0, a, b, +1), rbm1 = rb_pm(dn + 1.0, a, b, -1);
+    const double rbip = n >= 1 ? 1.0 / rb_pm(dn, a, b, +1) : 0.0;
+    const double rbim = n >= 1 ? 1.0 / rb_pm(dn, a, b, -1) : 0.0;
+    fp[n] = make_double4(A, C1 * rbp1, rbip, 0.0);
+    fm[n] = make_double4(A, C1 * rbm1, rbim, 0.0);
+    const double hp = n >= 1 ? C / rf_pm(dn - 1.0, a, b, +1) : 0.0;
+    const double hm = n >= 1 ? C / rf_pm(dn - 1.0, a, b, -1) : 0.0;
+    ip[n] = make_double4(A, hp, rf_pm(dn, a, b, +1), 0.0);
+    im[n] = make_double4(A, hm, rf_pm(dn, a, b, -1), 0.0);
+}
+
+// C_{n,m}, m < M, for n >= nlo (zero below): eq. Cnmabasy at m = 0, then the
+// m-step of eq. Cnmabrec.
+__global__ void k_plan_C(int64_t N, double a, double b, int M, int64_t nlo, double* C)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n > N) return;
+    if (n < nlo) {
+        for (int m = 0; m < M; ++m) C[(int64_t)m * (N + 1) + n] = 0.0;
+        return;
+    }
+    const double dn = (double)n;
+    double c = hahn_C(dn, 0, a, b);
+    C[n] = c;
+    for (int m = 1; m < M; ++m) {
+        c /= 2.0 * (2.0 * dn + a + b + m + 1.0);
+        C[(int64_t)m * (N + 1) + n] = c;
+    }
+}
+
+// (u_m, v_m)(theta_i), theta_i = pi i / G, on [lo, hi] (zero elsewhere), from
+//   u_m + i v_m = sum_l a_l b_{m-l} exp(i theta_{m,l}) / (sin^{l+a+1/2}(theta/2) cos^{m-l+b+1/2}(theta/2))
+// with theta_{m,l} = (a + l + 1/2) pi/2 - (a + b + m + 1) theta/2 (Sec. 2.1, eq. Jacasyuv):
+// = K c^-m e^{i phi_0} e^{-i m theta/2} sum_l a_l b_{m-l} (i t)^l,
+//   t = cot(theta/2), K = s^-(a+1/2) c^-(b+1/2), phi_0 = (a+1/2) pi/2 - (a+b+1) theta/2.
+__global__ void k_plan_uv(int64_t G, double a, double b, int M, int64_t lo, int64_t hi, cx<double>* uv)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > G) return;
+    if (i < lo || i > hi || i <= 0 || i >= G) {
+        for (int m = 0; m < M; ++m) uv[(int64_t)m * (G + 1) + i] = {0.0, 0.0};
+        return;
+    }
+    double ca[kMaxM + 1], cb[kMaxM + 1];
+    hahn_pochhammer(M, a, b, ca, cb);
+    double s, c;
+    sincospi((double)i / (double)(2 * G), &s, &c);
+    const double t = c / s;
+    const double K = exp(-(a + 0.5) * log(s) - (b + 0.5) * log(c));
+    double e0s, e0c;
+    sincospi(0.5 * (a + 0.5) - (a + b + 1.0) * (double)i / (double)(2 * G), &e0s, &e0c);
+    double tp[kMaxM + 1];
+    tp[0] = 1.0;
+    for (int l = 1; l < M; ++l) tp[l] = tp[l - 1] * t;
+    double cm = K;  // K c^-m
+    const double ic = 1.0 / c;
+    const int64_t fourG = 4 * G;
+    for (int m = 0; m < M; ++m) {
+        double wr = 0.0, wi = 0.0;
+        for (int l = 0; l <= m; ++l) {
+            const double term = ca[l] * cb[m - l] * tp[l];
+            switch (l & 3) {
+                case 0: wr += term; break;
+                case 1: wi += term; break;
+                case 2: wr -= term; break;
+                default: wi -= term; break;
+            }
+        }
+        // e^{-i pi m i / (2G)} from the exact rational angle
+        const int64_t r = ((int64_t)m * i) % fourG;
+        double rs, rc;
+        sincospi((double)r / (double)(2 * G), &rs, &rc);
+        // e^{i phi_0} e^{-i m theta/2}
+        const double er = e0c * rc + e0s * rs;
+        const double ei = e0s * rc - e0c * rs;
+        const double vr = cm * (er * wr - ei * wi);
+        const double vi = cm * (er * wi + ei * wr);
+        uv[(int64_t)m * (G + 1) + i] = {vr, vi};
+        cm *= ic;
+    }
+}
+
+// s_n = 1 / A_n (eq. Anab via eq. Anabasy).
+__global__ void k_plan_s(int64_t N, double a, double b, double* s)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n > N) return;
+    s[n] = 1.0 / jacobi_norm((double)n, a, b);
+}
+
+// ------------------------------------------------------------------ host plan build
+
+// Modified Chebyshev moments of the Jacobi weight (Sec. 3.1): mu_0 from the
+// Beta function, mu_1 = (b - a)/(a + b + 2) mu_0 (integration by parts; the
+// printed (a - b) has the wrong sign), then the forward three-term recurrence.
+static void moments_host(int64_t L, double a, double b, std::vector<double>* mu)
+{
+    mu->assign(L + 1, 0.0);
+    (*mu)[0] = exp2(a + b + 1.0) * tgamma(a + 1.0) * tgamma(b + 1.0) / tgamma(a + b + 2.0);
+    if (L >= 1) (*mu)[1] = (b - a) / (a + b + 2.0) * (*mu)[0];
+    for (int64_t n = 1; n < L; ++n) {
+        const double dn = (double)n;
+        (*mu)[n + 1] = -(2.0 * (a - b) * (*mu)[n] + (a + b - dn + 2.0) * (*mu)[n - 1]) / (a + b + dn + 2.0);
+    }
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+cjt_status build_plan_device(Plan* P, hipStream_t st)
+{
+    const int64_t N = P->N;
+    const int M = std::max(P->fwd.M, P->inv.M);
+    const int64_t nf = N + 1, ni = 2 * N + 1;
+    // layout
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    const size_t oC = take(sizeof(double) * (size_t)M * nf);
+    const size_t oUVf = take(sizeof(cx<double>) * (size_t)P->fwd.M * nf);
+    const size_t oUVi = take(sizeof(cx<double>) * (size_t)P->inv.M * ni);
+    const size_t oW = take(sizeof(double) * ni);
+    const size_t oS = take(sizeof(double) * nf);
+    const size_t oR = take(sizeof(double4) * 6 * (size_t)nf);
+    const size_t oTf = take(sizeof(RecTask) * std::max<size_t>(1, P->tasks_f.size()));
+    const size_t oTi = take(sizeof(RecTask) * std::max<size_t>(1, P->tasks_i.size()));
+    const size_t oMu = take(sizeof(double) * ni);
+    P->arena_bytes = off;
+    CJT_HIP_TRY(hipMalloc(&P->arena, off));
+    char* base = (char*)P->arena;
+    P->C = (double*)(base + oC);
+    P->uv_f = (cx<double>*)(base + oUVf);
+    P->uv_i = (cx<double>*)(base + oUVi);
+    P->w = (double*)(base + oW);
+    P->s = (double*)(base + oS);
+    double4* R = (double4*)(base + oR);
+    P->f0 = R;
+    P->fp = R + nf;
+    P->fm = R + 2 * nf;
+    P->i0 = R + 3 * nf;
+    P->ip = R + 4 * nf;
+    P->im = R + 5 * nf;
+    P->d_tasks_f = (RecTask*)(base + oTf);
+    P->d_tasks_i = (RecTask*)(base + oTi);
+    double* mu = (double*)(base + oMu);
+
+    const double a = P->alpha, b = P->beta;
+    const unsigned bs = 256;
+    auto grid = [&](int64_t n) { return dim3((unsigned)((n + bs - 1) / bs)); };
+    hipLaunchKernelGGL(k_plan_rec, grid(nf), dim3(bs), 0, st, N, a, b, P->f0, P->fp, P->fm, P->i0, P->ip, P->im);
+    CJT_HIP_TRY(hipGetLastError());
+    int64_t nlo = N + 1;
+    for (int k = 0; k < P->fwd.nblk; ++k) nlo = std::min(nlo, P->fwd.deg_lo[k]);
+    for (int k = 0; k < P->inv.nblk; ++k) nlo = std::min(nlo, P->inv.deg_lo[k]);
+    hipLaunchKernelGGL(k_plan_C, grid(nf), dim3(bs), 0, st, N, a, b, M, nlo, P->C);
+    CJT_HIP_TRY(hipGetLastError());
+    const int64_t flo = P->fwd.nblk ? P->fwd.win_lo[0] : 1, fhi = P->fwd.nblk ? P->fwd.win_hi[0] : 0;
+    hipLaunchKernelGGL(k_plan_uv, grid(nf), dim3(bs), 0, st, N, a, b, P->fwd.M, flo, fhi, P->uv_f);
+    CJT_HIP_TRY(hipGetLastError());
+    const int64_t ilo = P->inv.nblk ? P->inv.win_lo[0] : 1, ihi = P->inv.nblk ? P->inv.win_hi[0] : 0;
+    hipLaunchKernelGGL(k_plan_uv, grid(ni), dim3(bs), 0, st, 2 * N, a, b, P->inv.M, ilo, ihi, P->uv_i);
+    CJT_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_plan_s, grid(nf), dim3(bs), 0, st, N, a, b, P->s);
+    CJT_HIP_TRY(hipGetLastError());
+    if (!P->tasks_f.empty())
+        CJT_HIP_TRY(hipMemcpyAsync(P->d_tasks_f, P->tasks_f.data(), sizeof(RecTask) * P->tasks_f.size(),
+                                   hipMemcpyHostToDevice, st));
+    if (!P->tasks_i.empty())
+        CJT_HIP_TRY(hipMemcpyAsync(P->d_tasks_i, P->tasks_i.data(), sizeof(RecTask) * P->tasks_i.size(),
+                                   hipMemcpyHostToDevice, st));
+    std::vector<double> hmu;
+    moments_host(2 * N, a, b, &hmu);
+    CJT_HIP_TRY(hipMemcpyAsync(mu, hmu.data(), sizeof(double) * ni, hipMemcpyHostToDevice, st));
+    // Clenshaw--Curtis weights on the 2N grid: one DCT-I of the moments.
+    ExecDesc d{};
+    d.N = N;
+    d.G = 2 * N;
+    d.alpha = a;
+    d.beta = b;
+    d.in = mu;
+    d.out = P->w;
+    ExecDesc* dd = nullptr;
+    CJT_HIP_TRY(hipMalloc(&dd, sizeof(ExecDesc)));
+    cjt_status stt = CJT_OK;
+    do {
+        if (hipMemcpyAsync(dd, &d, sizeof(ExecDesc), hipMemcpyHostToDevice, st) != hipSuccess) {
+            stt = fail(CJT_EDEVICE, "descriptor copy failed");
+            break;
+        }
+        EngineArgs ea{};
+        ea.d_desc = dd;
+        ea.count = 1;
+        ea.max_jobs = 1;
+        stt = fft_geometry(2 * N, false, st, &ea.geom);
+        if (stt != CJT_OK) break;
+        ea.stream = st;
+        // two-pass transforms need an intermediate buffer
+        void* tmp = nullptr;
+        if (!ea.geom.single) {
+            if (hipMalloc(&tmp, sizeof(cx<double>) * (size_t)(2 * N)) != hipSuccess) {
+                stt = fail(CJT_ENOMEM, "weights workspace");
+                break;
+            }
+            d.tmp = tmp;
+            if (hipMemcpyAsync(dd, &d, sizeof(ExecDesc), hipMemcpyHostToDevice, st) != hipSuccess) {
+                stt = fail(CJT_EDEVICE, "descriptor copy failed");
+                break;
+            }
+        }
+        stt = launch_rdft(ea, Src::Moments, Sink::Weights, false);
+        if (hipStreamSynchronize(st) != hipSuccess && stt == CJT_OK) stt = fail(CJT_EDEVICE, "plan build failed");
+        if (tmp) (void)hipFree(tmp);
+    } while (0);
+    (void)hipFree(dd);
+    if (stt != CJT_OK) return stt;
+    CJT_HIP_TRY(hipStreamSynchronize(st));
+    return CJT_OK;
+}
+
+// ------------------------------------------------------------------ FFT geometry cache
+
+namespace {
+struct TwKey {
+    int dev;
+    int64_t L;
+    bool fp32;
+    bool operator<(const TwKey& o) const
+    {
+        if (dev != o.dev) return dev < o.dev;
+        if (L != o.L) return L < o.L;
+        return fp32 < o.fp32;
+    }
+};
+std::mutex g_tw_mu;
+std::vector<std::pair<TwKey, const void*>> g_tw;
+}  // namespace
+
+cjt_status fft_geometry(int64_t L, bool fp32, hipStream_t st, FftGeom* g)
+{
+    if (L < 1 || (L & (L - 1)) != 0) return fail(CJT_EUNSUPPORTED, "FFT length must be a power of two");
+    int dev = 0;
+    CJT_HIP_TRY(hipGetDevice(&dev));
+    const void* tw = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_tw_mu);
+        for (auto& e : g_tw)
+            if (e.first.dev == dev && e.first.L == L && e.first.fp32 == fp32) tw = e.second;
+        if (!tw) {
+            cjt_status s = make_twiddles(L, fp32, &tw, st);
+            if (s != CJT_OK) return s;
+            CJT_HIP_TRY(hipStreamSynchronize(st));
+            g_tw.push_back({TwKey{dev, L, fp32}, tw});
+        }
+    }
+    *g = FftGeom{};
+    g->L = L;
+    int lg = 0;
+    while (((int64_t)1 << lg) < L) ++lg;
+    g->logL = lg;
+    g->tw = tw;
+    g->single = L <= kSingleMax ? 1 : 0;
+    if (!g->single) {
+        g->logL1 = lg / 2;
+        g->logL2 = lg - g->logL1;
+        g->L1 = 1 << g->logL1;
+        g->L2 = 1 << g->logL2;
+    }
+    return CJT_OK;
+}
+
+}  // namespace cjt

@@ -1,0 +1,491 @@
+// Real-input DFTs behind every DCT-I / DST-I of the transform.
+//
+// All of them have the form
+//     X_s = sum_{q < 2L} r_q exp(+i pi q s / L),   s = 0..L,   r real,
+// computed from one complex FFT of length L on z_t = r_{2t} + i r_{2t+1}
+// followed by the standard untangling
+//     X_s = E_s + e^{i pi s/L} O_s,   E_s = (Z_s + conj Z_{L-s})/2,   O_s = (Z_s - conj Z_{L-s})/(2i).
+// Re X is a DCT-I and Im X a DST-I of the same data (Sec. 2.1: T_N is a
+// diagonally scaled DCT-I, the sine matrix a DST-I bordered by zeros).
+//
+// What r is and what happens to X is set by a source and a sink:
+//   FwdAsy  / FwdAsy : the Hahn blocks of the forward transform (eq. PNASY):
+//                      r_n = C_{n,m} c_n on the block's degrees, and
+//                      p_i += u_m(theta_i) Re X_i + v_m(theta_i) Im X_i on its window;
+//   InvAsy  / InvAsy : the transposed blocks of the inverse (Sec. 3.2): r built
+//                      from a_j = u_m g_j, b_j = v_m g_j on the window so that
+//                      Re X_n + Im X_n = sum_j a_j cos(pi n j/2N) + b_j sin(pi n j/2N),
+//                      and y_n = sum_m C_{n,m} (...) on the block's degrees;
+//   FwdFinal/ FwdFinal: c_cheb = T_N^{-1} p (diagonally scaled DCT-I);
+//   InvInit / InvInit : g_j = w_j f_j with f = T_{2N}^T [c_cheb; 0] (eq. CJTT);
+//   Moments / Weights : Clenshaw--Curtis weights from modified moments (eq. CCweights).
+//
+// Lengths up to kSingleMax run in one workgroup (whole transform in LDS);
+// longer ones in two passes L = L1 * L2: a column pass (L1-point FFTs over
+// stride L2, times exp(2 pi i n2 k1 / L)) writes intermediates to global memory,
+// and a row pass (L2-point FFTs) pairs rows k1 and L1-k1 so each workgroup has
+// both Z_s and Z_{L-s} for the untangling.  The row pass loops over all Hahn
+// terms (m) and blocks (k) of its rows and accumulates in registers, so each
+// output is written once.
+#include "cjt_internal.h"
+#include "fft_lds.h"
+
+namespace cjt {
+
+// ------------------------------------------------------------------ sources
+
+template <Src S>
+struct Source;
+
+template <>
+struct Source<Src::FwdAsy> {
+    // job = k * M + m
+    __device__ static bool valid(const ExecDesc& d, int job) { return job < d.nblk * d.M; }
+    __device__ static cx<double> load(const ExecDesc& d, int job, int64_t t)
+    {
+        const int k = job / d.M, m = job - k * d.M;
+        const int64_t lo = d.deg_lo[k], hi = d.deg_hi[k];
+        const int64_t n0 = 2 * t, n1 = n0 + 1;
+        const double* Cm = d.C + (int64_t)m * (d.N + 1);
+        double x0 = (n0 >= lo && n0 < hi) ? Cm[n0] * d.in[n0] : 0.0;
+        double x1 = (n1 >= lo && n1 < hi) ? Cm[n1] * d.in[n1] : 0.0;
+        return {x0, x1};
+    }
+};
+
+template <>
+struct Source<Src::InvAsy> {
+    __device__ static bool valid(const ExecDesc& d, int job) { return job < d.nblk * d.M; }
+    // a_j = u_m(theta_j) g_j, b_j = v_m(theta_j) g_j on the window (zero elsewhere);
+    // r_0 = a_0, r_G = a_G, r_j = (a_j + b_j)/2 and r_{2G-j} = (a_j - b_j)/2 for 0 < j < G.
+    __device__ static double r(const ExecDesc& d, int k, const cx<double>* uvm, int64_t q)
+    {
+        const int64_t G = d.G;
+        int64_t j;
+        double sb;
+        if (q <= G) { j = q; sb = 1.0; }
+        else { j = 2 * G - q; sb = -1.0; }
+        if (j < d.win_lo[k] || j > d.win_hi[k]) return 0.0;
+        const double g = d.p[j];
+        const cx<double> uv = uvm[j];
+        if (j == 0 || j == G) return uv.re * g;
+        return 0.5 * (uv.re * g + sb * uv.im * g);
+    }
+    __device__ static cx<double> load(const ExecDesc& d, int job, int64_t t)
+    {
+        const int k = job / d.M, m = job - k * d.M;
+        const cx<double>* uvm = d.uv + (int64_t)m * (d.G + 1);
+        return {r(d, k, uvm, 2 * t), r(d, k, uvm, 2 * t + 1)};
+    }
+};
+
+template <>
+struct Source<Src::FwdFinal> {
+    __device__ static bool valid(const ExecDesc&, int job) { return job == 0; }
+    __device__ static cx<double> load(const ExecDesc& d, int, int64_t t)
+    {
+        const int64_t N = d.N, j0 = 2 * t, j1 = j0 + 1;
+        double x0 = j0 <= N ? d.p[j0] * ((j0 == 0 || j0 == N) ? 0.5 : 1.0) : 0.0;
+        double x1 = j1 <= N ? d.p[j1] * ((j1 == N) ? 0.5 : 1.0) : 0.0;
+        return {x0, x1};
+    }
+};
+
+template <>
+struct Source<Src::InvInit> {
+    __device__ static bool valid(const ExecDesc&, int job) { return job == 0; }
+    __device__ static cx<double> load(const ExecDesc& d, int, int64_t t)
+    {
+        const int64_t N = d.N, k0 = 2 * t, k1 = k0 + 1;
+        return {k0 <= N ? d.in[k0] : 0.0, k1 <= N ? d.in[k1] : 0.0};
+    }
+};
+
+template <>
+struct Source<Src::Moments> {
+    // in = mu_0..mu_G, halved at both ends
+    __device__ static bool valid(const ExecDesc&, int job) { return job == 0; }
+    __device__ static cx<double> load(const ExecDesc& d, int, int64_t t)
+    {
+        const int64_t G = d.G, k0 = 2 * t, k1 = k0 + 1;
+        double x0 = k0 <= G ? d.in[k0] * ((k0 == 0 || k0 == G) ? 0.5 : 1.0) : 0.0;
+        double x1 = k1 <= G ? d.in[k1] * ((k1 == G) ? 0.5 : 1.0) : 0.0;
+        return {x0, x1};
+    }
+};
+
+// ------------------------------------------------------------------ sinks
+// accumulate() sees every output index s in [0, L] exactly once per job;
+// slot identifies a register accumulator private to the calling thread.
+
+constexpr int kSlots = 20;
+constexpr int kEPT = 8;  // row-pass elements per thread: 2048 per 256-thread workgroup
+
+template <Sink S>
+struct Target;
+
+template <>
+struct Target<Sink::FwdAsy> {
+    __device__ static void accumulate(const ExecDesc& d, int job, int64_t i, cx<double> X, double* acc, int slot)
+    {
+        const int k = job / d.M, m = job - k * d.M;
+        if (i < d.win_lo[k] || i > d.win_hi[k]) return;
+        const cx<double> uv = d.uv[(int64_t)m * (d.G + 1) + i];
+        acc[slot] = fma(uv.re, X.re, fma(uv.im, X.im, acc[slot]));
+    }
+    __device__ static void finish(const ExecDesc& d, int64_t i, double v) { d.p[i] += v; }
+    static constexpr bool kNeedsAll = false;  // only indices inside some window matter
+};
+
+template <>
+struct Target<Sink::InvAsy> {
+    __device__ static void accumulate(const ExecDesc& d, int job, int64_t n, cx<double> X, double* acc, int slot)
+    {
+        const int k = job / d.M, m = job - k * d.M;
+        if (n < d.deg_lo[k] || n >= d.deg_hi[k]) return;
+        acc[slot] = fma(d.C[(int64_t)m * (d.N + 1) + n], X.re + X.im, acc[slot]);
+    }
+    // Every degree 0..N is written (zero outside the blocks); the recurrence
+    // reduction adds its part and applies 1/A_n afterwards.
+    __device__ static void finish(const ExecDesc& d, int64_t n, double v)
+    {
+        if (n <= d.N) d.out[n] = v;
+    }
+};
+
+template <>
+struct Target<Sink::FwdFinal> {
+    __device__ static void accumulate(const ExecDesc&, int, int64_t, cx<double> X, double* acc, int slot)
+    {
+        acc[slot] = X.re;
+    }
+    __device__ static void finish(const ExecDesc& d, int64_t k, double v)
+    {
+        const int64_t N = d.N;
+        const double sc = (k == 0 || k == N) ? 1.0 / (double)N : 2.0 / (double)N;
+        d.out[k] = sc * v;
+    }
+};
+
+template <>
+struct Target<Sink::InvInit> {
+    __device__ static void accumulate(const ExecDesc&, int, int64_t, cx<double> X, double* acc, int slot)
+    {
+        acc[slot] = X.re;
+    }
+    __device__ static void finish(const ExecDesc& d, int64_t j, double v) { d.p[j] = d.w[j] * v; }
+};
+
+template <>
+struct Target<Sink::Weights> {
+    __device__ static void accumulate(const ExecDesc&, int, int64_t, cx<double> X, double* acc, int slot)
+    {
+        acc[slot] = X.re;
+    }
+    // w_j = (1 - (d_j0 + d_jG)/2) / (G/2) Re X_j
+    __device__ static void finish(const ExecDesc& d, int64_t j, double v)
+    {
+        const int64_t G = d.G;
+        const double sc = ((j == 0 || j == G) ? 0.5 : 1.0) / (0.5 * (double)G);
+        d.out[j] = sc * v;
+    }
+};
+
+// ------------------------------------------------------------------ untangling
+
+template <typename T>
+struct Untangled {
+    cx<double> xa, xb;  // X_s and X_{L-s}
+};
+
+// From Z_s, Z_{L-s} (s not 0, not L/2): X_s = E + W O, X_{L-s} = conj(E - W O), W = tw[s].
+template <typename T>
+__device__ __forceinline__ void untangle(cx<T> za, cx<T> zb, cx<T> w, cx<double>& xs, cx<double>& xls)
+{
+    cx<T> zbc = conj(zb);
+    cx<T> e = {(T)0.5 * (za.re + zbc.re), (T)0.5 * (za.im + zbc.im)};
+    cx<T> dd = {(T)0.5 * (za.re - zbc.re), (T)0.5 * (za.im - zbc.im)};
+    cx<T> o = cmul_mi(dd);  // (za - conj zb) / (2i)
+    cx<T> wo = cmul(w, o);
+    xs = {(double)(e.re + wo.re), (double)(e.im + wo.im)};
+    xls = {(double)(e.re - wo.re), -(double)(e.im - wo.im)};
+}
+
+// ------------------------------------------------------------------ single pass
+
+template <typename T>
+__device__ __forceinline__ cx<T> to_t(cx<double> v) { return {(T)v.re, (T)v.im}; }
+
+// One workgroup per instance; the whole length-L transform lives in LDS.
+// Loops over all jobs of the instance and accumulates per thread.
+template <typename T, Src S, Sink K>
+__global__ void __launch_bounds__(256) k_single(const ExecDesc* __restrict__ descs, FftGeom g, int max_jobs)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const ExecDesc& d = descs[blockIdx.x];
+    const int L = (int)g.L;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
+    const int nel = L / 2 + 1;  // elements s = 0..L/2
+    double acc[kSlots];
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) acc[i] = 0.0;
+
+    for (int job = 0; job < max_jobs; ++job) {
+        if (!Source<S>::valid(d, job)) break;
+        for (int t = tid; t < L; t += nth) buf[lds_pad(t)] = to_t<T>(Source<S>::load(d, job, t));
+        __syncthreads();
+        lds_fft<T>(buf, g.logL, 1, tw, 2 * g.L);
+#pragma unroll
+        for (int q = 0; q < kSlots / 2; ++q) {
+            const int s = tid + q * nth;
+            if (s >= nel) break;
+            cx<double> xa, xb;
+            if (s == 0) {
+                cx<T> z = buf[lds_pad(0)];
+                xa = {(double)z.re + (double)z.im, 0.0};
+                xb = {(double)z.re - (double)z.im, 0.0};
+            } else if (2 * s == L) {
+                cx<T> z = buf[lds_pad(s)];
+                xa = {(double)z.re, (double)z.im};
+                xb = xa;
+            } else {
+                untangle<T>(buf[lds_pad(s)], buf[lds_pad(L - s)], tw[s], xa, xb);
+            }
+            Target<K>::accumulate(d, job, s, xa, acc, 2 * q);
+            if (2 * s != L) Target<K>::accumulate(d, job, L - s, xb, acc, 2 * q + 1);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < kSlots / 2; ++q) {
+        const int s = tid + q * nth;
+        if (s >= nel) break;
+        Target<K>::finish(d, s, acc[2 * q]);
+        if (2 * s != L) Target<K>::finish(d, L - s, acc[2 * q + 1]);
+    }
+}
+
+// ------------------------------------------------------------------ two passes
+
+// Column pass: TC consecutive columns n2 per workgroup, L1-point FFTs over n1,
+// multiply by exp(2 pi i n2 k1 / L), write tmp[job][k1 * L2 + n2].
+template <typename T, Src S>
+__global__ void __launch_bounds__(256) k_pass1(const ExecDesc* __restrict__ descs, FftGeom g, int TC)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const ExecDesc& d = descs[blockIdx.z];
+    const int job = blockIdx.y;
+    if (!Source<S>::valid(d, job)) return;
+    const int L1 = g.L1, L2 = g.L2;
+    const int64_t L = g.L;
+    const int col0 = blockIdx.x * TC;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
+    const int total = TC * L1;
+    for (int e = tid; e < total; e += nth) {
+        const int c = e % TC, n1 = e / TC;
+        const int64_t t = (int64_t)n1 * L2 + col0 + c;
+        buf[lds_pad(c * L1 + n1)] = to_t<T>(Source<S>::load(d, job, t));
+    }
+    __syncthreads();
+    lds_fft<T>(buf, g.logL1, TC, tw, 2 * L);
+    cx<T>* out = reinterpret_cast<cx<T>*>(d.tmp) + (int64_t)job * L;
+    for (int e = tid; e < total; e += nth) {
+        const int c = e % TC, k1 = e / TC;
+        const int64_t n2 = col0 + c;
+        const int64_t q = (2 * n2 * k1) & (2 * L - 1);  // exp(2 pi i n2 k1 / L) = tw[2 n2 k1 mod 2L]
+        out[(int64_t)k1 * L2 + n2] = cmul(buf[lds_pad(c * L1 + k1)], tw[q]);
+    }
+}
+
+// Row pass: TU units per workgroup; unit u holds rows u and L1-u (unit 0 holds
+// rows 0 and L1/2).  Element (u, k2) pairs Z at row u, position k2 with Z at
+// row L1-u, position L2-1-k2, which are Z_s and Z_{L-s} for s = u + L1 k2.
+template <typename T, Sink K>
+__global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ descs, FftGeom g, int TU, int max_jobs,
+                                               int src_single_job)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const ExecDesc& d = descs[blockIdx.z];
+    const int L1 = g.L1, L2 = g.L2;
+    const int64_t L = g.L;
+    const int unit0 = blockIdx.x * TU;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
+    // TU * L2 = 2048 regular elements per workgroup, kEPT = 8 per thread
+    constexpr int ept = kEPT;
+    const bool has_half = (unit0 == 0) && (tid == nth - 1);  // thread that also owns s = L/2
+
+    double acc[kSlots];
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) acc[i] = 0.0;
+
+    const int njobs = src_single_job ? 1 : max_jobs;
+    for (int job = 0; job < njobs; ++job) {
+        if (!src_single_job && job >= d.nblk * d.M) break;
+        const cx<T>* in = reinterpret_cast<const cx<T>*>(d.tmp) + (int64_t)job * L;
+        // load 2*TU rows of L2
+        for (int e = tid; e < 2 * TU * L2; e += nth) {
+            const int r = e / L2, pos = e - r * L2;
+            const int lu = r >> 1;
+            const int unit = unit0 + lu;
+            const int row = (r & 1) == 0 ? unit : (unit == 0 ? L1 / 2 : L1 - unit);
+            buf[lds_pad(r * L2 + pos)] = in[(int64_t)row * L2 + pos];
+        }
+        __syncthreads();
+        lds_fft<T>(buf, g.logL2, 2 * TU, tw, 2 * L);
+#pragma unroll
+        for (int q = 0; q < ept; ++q) {
+            const int eps = tid + q * nth;
+            const int lu = eps % TU, k2 = eps / TU;
+            const int unit = unit0 + lu;
+            const int ra = 2 * lu, rb = 2 * lu + 1;
+            cx<double> xa, xb;
+            int64_t s;
+            if (unit == 0) {
+                if (k2 < L2 / 2) {
+                    s = L1 / 2 + (int64_t)L1 * k2;
+                    untangle<T>(buf[lds_pad(rb * L2 + k2)], buf[lds_pad(rb * L2 + L2 - 1 - k2)], tw[s], xa, xb);
+                } else if (k2 == L2 / 2) {
+                    s = 0;
+                    cx<T> z = buf[lds_pad(ra * L2)];
+                    xa = {(double)z.re + (double)z.im, 0.0};
+                    xb = {(double)z.re - (double)z.im, 0.0};
+                } else {
+                    const int kk = k2 - L2 / 2;
+                    s = (int64_t)L1 * kk;
+                    untangle<T>(buf[lds_pad(ra * L2 + kk)], buf[lds_pad(ra * L2 + L2 - kk)], tw[s], xa, xb);
+                }
+            } else {
+                s = unit + (int64_t)L1 * k2;
+                untangle<T>(buf[lds_pad(ra * L2 + k2)], buf[lds_pad(rb * L2 + L2 - 1 - k2)], tw[s], xa, xb);
+            }
+            Target<K>::accumulate(d, job, s, xa, acc, 2 * q);
+            Target<K>::accumulate(d, job, L - s, xb, acc, 2 * q + 1);
+        }
+        if (has_half) {
+            cx<T> z = buf[lds_pad(0 * L2 + L2 / 2)];  // row 0, position L2/2: s = L/2
+            Target<K>::accumulate(d, job, L / 2, cx<double>{(double)z.re, (double)z.im}, acc, kSlots - 1);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < ept; ++q) {
+        const int eps = tid + q * nth;
+        const int lu = eps % TU, k2 = eps / TU;
+        const int unit = unit0 + lu;
+        int64_t s;
+        if (unit == 0) {
+            if (k2 < L2 / 2) s = L1 / 2 + (int64_t)L1 * k2;
+            else if (k2 == L2 / 2) s = 0;
+            else s = (int64_t)L1 * (k2 - L2 / 2);
+        } else {
+            s = unit + (int64_t)L1 * k2;
+        }
+        Target<K>::finish(d, s, acc[2 * q]);
+        Target<K>::finish(d, L - s, acc[2 * q + 1]);
+    }
+    if (has_half) Target<K>::finish(d, L / 2, acc[kSlots - 1]);
+}
+
+// ------------------------------------------------------------------ launch
+
+namespace {
+
+size_t lds_bytes(int n_elems, size_t esz) { return (size_t)(n_elems + (n_elems >> 4) + 1) * esz; }
+
+// Workgroups of this engine use up to ~70 KB of LDS (gfx950 has 160 KB per CU);
+// raise the dynamic-LDS limit of each kernel once before its first launch.
+template <typename K>
+cjt_status allow_lds(K kernel, size_t bytes)
+{
+    CJT_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    return CJT_OK;
+}
+
+template <typename T, Src S, Sink K>
+cjt_status run(const EngineArgs& a)
+{
+    const FftGeom& g = a.geom;
+    const size_t esz = sizeof(cx<T>);
+    const bool single_job = (S != Src::FwdAsy && S != Src::InvAsy);
+    const int max_jobs = single_job ? 1 : a.max_jobs;
+    if (max_jobs <= 0 || a.count <= 0) return CJT_OK;
+    if (g.single) {
+        const int L = (int)g.L;
+        int nth = L / 16;
+        if (nth < 64) nth = 64;
+        if (nth > 256) nth = 256;
+        if ((L / 2 + 1 + nth - 1) / nth > kSlots / 2) return fail(CJT_EUNSUPPORTED, "single-pass length too large");
+        cjt_status st = allow_lds(k_single<T, S, K>, lds_bytes(L, esz));
+        if (st != CJT_OK) return st;
+        hipLaunchKernelGGL((k_single<T, S, K>), dim3(a.count), dim3(nth), lds_bytes(L, esz), a.stream, a.d_desc, g,
+                           max_jobs);
+        CJT_HIP_TRY(hipGetLastError());
+        return CJT_OK;
+    }
+    // two passes; all workgroups use 256 threads (16 values per thread per stage)
+    const int per_wg = 256 * 16;                 // complex values held per workgroup
+    const int TC = per_wg / g.L1;                // columns per pass-1 workgroup
+    const int TU = per_wg / (2 * g.L2);          // row pairs per pass-2 workgroup
+    if (TC < 1 || TU < 1 || g.L2 % TC != 0 || (g.L1 / 2) % TU != 0)
+        return fail(CJT_EUNSUPPORTED, "FFT split not supported");
+    if (TU * g.L2 != 256 * kEPT) return fail(CJT_EUNSUPPORTED, "row pass geometry");
+    cjt_status st = allow_lds(k_pass1<T, S>, lds_bytes(per_wg, esz));
+    if (st == CJT_OK) st = allow_lds(k_pass2<T, K>, lds_bytes(per_wg, esz));
+    if (st != CJT_OK) return st;
+    dim3 g1(g.L2 / TC, max_jobs, a.count);
+    hipLaunchKernelGGL((k_pass1<T, S>), g1, dim3(256), lds_bytes(per_wg, esz), a.stream, a.d_desc, g, TC);
+    CJT_HIP_TRY(hipGetLastError());
+    dim3 g2((g.L1 / 2) / TU, 1, a.count);
+    hipLaunchKernelGGL((k_pass2<T, K>), g2, dim3(256), lds_bytes(per_wg, esz), a.stream, a.d_desc, g, TU, max_jobs,
+                       single_job ? 1 : 0);
+    CJT_HIP_TRY(hipGetLastError());
+    return CJT_OK;
+}
+
+}  // namespace
+
+cjt_status launch_rdft(const EngineArgs& a, Src src, Sink sink, bool fp32)
+{
+    if (src == Src::FwdAsy && sink == Sink::FwdAsy)
+        return fp32 ? run<float, Src::FwdAsy, Sink::FwdAsy>(a) : run<double, Src::FwdAsy, Sink::FwdAsy>(a);
+    if (src == Src::InvAsy && sink == Sink::InvAsy)
+        return fp32 ? run<float, Src::InvAsy, Sink::InvAsy>(a) : run<double, Src::InvAsy, Sink::InvAsy>(a);
+    if (src == Src::FwdFinal && sink == Sink::FwdFinal) return run<double, Src::FwdFinal, Sink::FwdFinal>(a);
+    if (src == Src::InvInit && sink == Sink::InvInit) return run<double, Src::InvInit, Sink::InvInit>(a);
+    if (src == Src::Moments && sink == Sink::Weights) return run<double, Src::Moments, Sink::Weights>(a);
+    return fail(CJT_EINVAL, "unknown transform pairing");
+}
+
+// tw[q] = exp(i pi q / L), q < 2L
+template <typename T>
+__global__ void k_twiddle(cx<T>* tw, int64_t L)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 2 * L) return;
+    double s, c;
+    sincospi((double)q / (double)L, &s, &c);
+    tw[q] = {(T)c, (T)s};
+}
+
+cjt_status make_twiddles(int64_t L, bool fp32, const void** out, hipStream_t stream)
+{
+    void* p = nullptr;
+    const size_t bytes = (size_t)(2 * L) * (fp32 ? sizeof(cx<float>) : sizeof(cx<double>));
+    CJT_HIP_TRY(hipMalloc(&p, bytes));
+    const int64_t n = 2 * L;
+    dim3 grid((unsigned)((n + 255) / 256));
+    if (fp32) hipLaunchKernelGGL(k_twiddle<float>, grid, dim3(256), 0, stream, (cx<float>*)p, L);
+    else hipLaunchKernelGGL(k_twiddle<double>, grid, dim3(256), 0, stream, (cx<double>*)p, L);
+    CJT_HIP_TRY(hipGetLastError());
+    *out = p;
+    return CJT_OK;
+}
+
+}  // namespace cjt
