@@ -1,0 +1,200 @@
+"""Benchmark: batched forward + inverse Chebyshev--Jacobi transforms on one MI355X.
+
+Workload (default): 256 independent transforms at N = 65536 with
+(alpha, beta) ~ U(-1/2, 1/2)^2 per instance and c_n = z_n / (n+1), z ~ N(0,1)
+(seeded, synthetic; the paper's experiments use the same kind of inputs).
+One step = one batched forward transform of all 256 coefficient vectors
+followed by one batched inverse transform of its output.  Inputs, outputs and
+plans are resident in HBM before timing starts; plans are built once.
+
+Prints one JSON line.  `value` is coefficients/s of the FP64 path,
+2 * 256 * (N+1) per step; the FP32-bulk path (FP32 DCT-I/DST-I in the Hahn
+blocks) is reported beside it.  `roofline` covers the kernel with the largest
+share of the FP64 step, timed with HIP events on its own stream over the timed
+steps; `cpu_baseline` times the CPU oracle on one instance (forward + inverse).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 vector
+PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--count", type=int, default=256, help="transforms per batch")
+    ap.add_argument("--N", type=int, default=65536)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_steps(torch, step, steps, warmup):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        step()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([a.elapsed_time(b) for a, b in evs])  # ms
+    return wall, per
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); independent transforms would shard "
+              "across GPUs with no exchange, but no multi-GPU path is built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1602_02618_amd import cjt, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cjt.load()
+    N, count = args.N, args.count
+    insts = inputs.batch_uniform_params(count, N, args.seed, r=1.0)
+    log(f"bench: {count} transforms at N={N}")
+
+    t0 = time.perf_counter()
+    plans64 = [cjt.cjt_plan(i.N, i.alpha, i.beta, 0, cjt.CJT_FP64) for i in insts]
+    t_plan64 = time.perf_counter() - t0
+    plans32 = []
+    t_plan32 = 0.0
+    if not args.no_fp32:
+        t0 = time.perf_counter()
+        plans32 = [cjt.cjt_plan(i.N, i.alpha, i.beta, 0, cjt.CJT_FP32_BULK) for i in insts]
+        t_plan32 = time.perf_counter() - t0
+    log(f"plans built: fp64 {t_plan64:.2f}s fp32-bulk {t_plan32:.2f}s")
+
+    offs = np.concatenate([[0], np.cumsum([i.N + 1 for i in insts])]).astype(np.int64)
+    x = torch.as_tensor(np.concatenate([i.coeffs for i in insts]), dtype=torch.float64, device="cuda")
+    f = torch.empty_like(x)
+    g = torch.empty_like(x)
+
+    def make_step(plans):
+        def step():
+            cjt.cjt_forward_batched(plans, offs, x, f)
+            cjt.cjt_inverse_batched(plans, offs, f, g)
+        return step
+
+    coeffs_per_step = 2 * int(offs[-1])
+    results = {}
+    for name, plans in (("fp64", plans64), ("fp32_bulk", plans32)):
+        if not plans:
+            continue
+        step = make_step(plans)
+        wall, per = time_steps(torch, step, args.steps, args.warmup)
+        # kernel breakdown over a second timed pass of the same steps
+        cjt.cjt_profile_enable(True)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        cjt.cjt_profile_enable(False)
+        kern = cjt.cjt_profile_collect()
+        f_h = f[: offs[1]].cpu().numpy().copy()
+        g_h = g[: offs[1]].cpu().numpy().copy()
+        results[name] = dict(wall=wall, per=per, kern=kern, f0=f_h, g0=g_h)
+        ms = wall / args.steps * 1e3
+        log(f"{name}: {ms:.3f} ms/step, {coeffs_per_step / (wall / args.steps):.4e} coeff/s, "
+            f"p50 {np.percentile(per, 50):.3f} ms p99 {np.percentile(per, 99):.3f} ms")
+        for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["total_ms"]):
+            log(f"   {k:28s} {v['total_ms'] / args.steps:8.3f} ms/step  "
+                f"{v['flops'] / (v['total_ms'] * 1e-3) / 1e12 if v['total_ms'] > 0 else 0:7.2f} TFLOP/s alg")
+
+    # FP32-bulk inverse on the FP64 forward output of instance 0 (same input as the FP64 inverse)
+    err = {}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        c0 = insts[0].coeffs
+        threads = oracle.default_threads()
+        t0 = time.perf_counter()
+        f_ref = oracle.forward(c0, insts[0].alpha, insts[0].beta, threads=threads)
+        g_ref = oracle.inverse(results["fp64"]["f0"], insts[0].alpha, insts[0].beta, threads=threads)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": 2 * (N + 1) / t_cpu, "unit": "coefficients/s", "cores": threads, "kind": "oracle",
+               "sample": f"instance 0 of the batch: one forward and one inverse transform at N={N} "
+                         f"(long double O(N^2) plain definition), {t_cpu:.1f} s"}
+        rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        err["fp64_forward"] = rel(results["fp64"]["f0"], f_ref)
+        err["fp64_inverse"] = rel(results["fp64"]["g0"], g_ref)
+        if "fp32_bulk" in results:
+            err["fp32_bulk_forward"] = rel(results["fp32_bulk"]["f0"], f_ref)
+            fin = torch.as_tensor(results["fp64"]["f0"], dtype=torch.float64, device="cuda")
+            g32 = cjt.inverse(plans32[0], fin).cpu().numpy()
+            err["fp32_bulk_inverse"] = rel(g32, g_ref)
+        err["tolerance_fp64"] = 1e-13 * math.log2(N)
+        log(f"errors vs oracle (instance 0): {err}; oracle {t_cpu:.1f}s on {threads} threads")
+
+    r64 = results["fp64"]
+    t_step = r64["wall"] / args.steps
+    kern = r64["kern"]
+    top = max(kern.items(), key=lambda kv: kv[1]["total_ms"])
+    tname, tv = top
+    achieved = tv["flops"] / (tv["total_ms"] * 1e-3) / 1e12
+    peak = PEAK_FP32_TFLOPS if tname.endswith("fp32") else PEAK_FP64_TFLOPS
+    out = {
+        "metric": "CJT coefficients/sec (fwd+inv) batched N=2^16; p99 latency; rel. error",
+        "value": coeffs_per_step / t_step,
+        "unit": "coefficients/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batch of {count} forward+inverse CJTs at N={N}, (alpha,beta)~U(-1/2,1/2)^2, "
+                               f"c_n=randn/(n+1)", "count": count, "N": N, "seed": args.seed,
+                   "parallelism": "single GPU"},
+        "p50_ms": float(np.percentile(r64["per"], 50)),
+        "p99_ms": float(np.percentile(r64["per"], 99)),
+        "rel_error": err,
+        "plan_s": {"fp64": t_plan64, "fp32_bulk": t_plan32},
+        "kernels_ms_per_step": {k: v["total_ms"] / args.steps for k, v in kern.items()},
+        "roofline": {"bound": "alu", "kernel": tname, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "alg_bytes_per_launch": tv["bytes"] / max(tv["launches"], 1),
+                     "alg_flops_per_launch": tv["flops"] / max(tv["launches"], 1)},
+        "cpu_baseline": cpu,
+    }
+    if "fp32_bulk" in results:
+        r32 = results["fp32_bulk"]
+        t32 = r32["wall"] / args.steps
+        out["fp32_bulk"] = {"value": coeffs_per_step / t32, "ms_per_step": t32 * 1e3,
+                            "p50_ms": float(np.percentile(r32["per"], 50)),
+                            "p99_ms": float(np.percentile(r32["per"], 99)),
+                            "speedup_vs_fp64": t_step / t32,
+                            "kernels_ms_per_step": {k: v["total_ms"] / args.steps for k, v in r32["kern"].items()}}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -137,6 +137,28 @@ const char* cjt_strerror(cjt_status status);
 /* Detail message of the last error on the calling thread ("" if none). */
 const char* cjt_last_error(void);
 
+/* Kernel timing (instrumentation).  While enabled, every kernel launch of the
+ * execution calls is bracketed by HIP events recorded on the caller's stream,
+ * and tagged with the algorithmic work of that launch: floating-point
+ * operations by a fixed convention (2.5 L log2 L per real FFT of length L,
+ * i.e. per DCT-I + DST-I pair of a Hahn block, plus 4 per diagonal scaling of
+ * a window point and 2 per coefficient scaling; 6 per three-term or
+ * Clenshaw--Smith step and 10 per modified step of Sec. 4.2) and the
+ * compulsory HBM bytes (each vector the kernel must read or write, once).  cjt_profile_collect waits for the
+ * device, sums time and work per kernel name into out[0 .. *n_out) (at most
+ * max entries) and clears the record.  Timing adds two event records per
+ * launch; leave it off outside measurement. */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+    double flops;        /* algorithmic flops over all launches */
+    double bytes;        /* compulsory HBM bytes over all launches */
+} cjt_kernel_stat;
+
+cjt_status cjt_profile_enable(int on);
+cjt_status cjt_profile_collect(cjt_kernel_stat* out, int max, int* n_out);
+
 /* Library version, as major*10000 + minor*100 + patch. */
 int cjt_version(void);
 

@@ -23,7 +23,7 @@ CJT_MAX_BLOCKS = 16
 _EXPORTS = (
     "cjt_plan", "cjt_forward", "cjt_inverse", "cjt_forward_batched", "cjt_inverse_batched",
     "cjt_plan_query", "cjt_plan_describe", "cjt_plan_destroy", "cjt_strerror", "cjt_last_error",
-    "cjt_version",
+    "cjt_version", "cjt_profile_enable", "cjt_profile_collect",
 )
 
 
@@ -46,6 +46,16 @@ class cjt_partition_info(ctypes.Structure):
     def blocks(self):
         """[(deg_lo, deg_hi, win_lo, win_hi), ...] for the nblocks Hahn blocks."""
         return [(self.deg_lo[k], self.deg_hi[k], self.win_lo[k], self.win_hi[k]) for k in range(self.nblocks)]
+
+
+class cjt_kernel_stat(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 48),
+        ("launches", ctypes.c_int64),
+        ("total_ms", ctypes.c_double),
+        ("flops", ctypes.c_double),
+        ("bytes", ctypes.c_double),
+    ]
 
 
 class cjt_plan_info(ctypes.Structure):
@@ -101,6 +111,10 @@ def load(path=LIB_PATH):
         lib.cjt_last_error.restype = ctypes.c_char_p
         lib.cjt_version.argtypes = []
         lib.cjt_version.restype = ci
+        lib.cjt_profile_enable.argtypes = [ci]
+        lib.cjt_profile_enable.restype = ci
+        lib.cjt_profile_collect.argtypes = [P(cjt_kernel_stat), ci, P(ci)]
+        lib.cjt_profile_collect.restype = ci
         for f in ("cjt_plan", "cjt_forward", "cjt_inverse", "cjt_forward_batched", "cjt_inverse_batched",
                   "cjt_plan_query", "cjt_plan_describe", "cjt_plan_destroy"):
             getattr(lib, f).restype = ci
@@ -232,6 +246,19 @@ def cjt_last_error():
 
 def cjt_version():
     return int(load().cjt_version())
+
+
+def cjt_profile_enable(on=True):
+    _check(load().cjt_profile_enable(1 if on else 0), "cjt_profile_enable")
+
+
+def cjt_profile_collect(max_entries=64):
+    """{name: dict(launches, total_ms, flops, bytes)} of the kernels timed since the last collect."""
+    arr = (cjt_kernel_stat * max_entries)()
+    n = ctypes.c_int(0)
+    _check(load().cjt_profile_collect(arr, max_entries, ctypes.byref(n)), "cjt_profile_collect")
+    return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms, flops=arr[i].flops,
+                                       bytes=arr[i].bytes) for i in range(n.value)}
 
 
 # ---------------------------------------------------------------- conveniences

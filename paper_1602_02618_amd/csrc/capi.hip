@@ -35,6 +35,61 @@ cjt_status fail(cjt_status st, const std::string& msg)
     return st;
 }
 
+// ------------------------------------------------------------------ kernel timing
+
+namespace {
+
+struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+    double flops, bytes;
+};
+
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_ev_pool;
+
+hipEvent_t ev_get()
+{
+    if (!g_ev_pool.empty()) {
+        hipEvent_t e = g_ev_pool.back();
+        g_ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one launch with events on `st` when timing is enabled.
+struct ProfScope {
+    bool on = false;
+    ProfRec r{};
+    hipStream_t st = nullptr;
+    ProfScope(const char* name, double flops, double bytes, hipStream_t s)
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (!g_prof_on) return;
+        r.name = name;
+        r.flops = flops;
+        r.bytes = bytes;
+        r.a = ev_get();
+        r.b = ev_get();
+        st = s;
+        if (!r.a || !r.b) return;
+        on = hipEventRecord(r.a, st) == hipSuccess;
+    }
+    ~ProfScope()
+    {
+        if (!on) return;
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (hipEventRecord(r.b, st) == hipSuccess) g_prof.push_back(r);
+    }
+};
+
+}  // namespace
+
 // ------------------------------------------------------------------ workspace (one per stream)
 
 namespace {
@@ -130,6 +185,34 @@ Need need_of(const Plan& P, bool inverse, bool fp32)
 }
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Algorithmic work of one transform's kernels (see cjt_profile_enable).
+struct Work {
+    double rec_flops = 0, asy_flops = 0, bnd_flops = 0;
+    double rec_bytes = 0, asy_bytes = 0, bnd_bytes = 0;
+};
+
+Work work_of(const Plan& P, bool inverse)
+{
+    Work w;
+    const Part& pt = inverse ? P.inv : P.fwd;
+    const std::vector<RecTask>& tasks = inverse ? P.tasks_i : P.tasks_f;
+    for (const RecTask& t : tasks) w.rec_flops += (double)t.np * (double)t.cut * (t.mode == 0 ? 6.0 : 10.0);
+    const double N = (double)P.N, Lr = inverse ? 4.0 * N : 2.0 * N;  // real FFT length
+    const double fft = 2.5 * Lr * log2(Lr);
+    for (int k = 0; k < pt.nblk; ++k) {
+        const double wk = (double)(pt.win_hi[k] - pt.win_lo[k] + 1), dk = (double)(pt.deg_hi[k] - pt.deg_lo[k]);
+        w.asy_flops += pt.M * (fft + 4.0 * wk + 2.0 * dk);
+    }
+    w.bnd_flops = fft + Lr / 2;
+    const double gN = inverse ? 2.0 * N + 1 : N + 1;  // grid points
+    // recurrence: coefficients in, point values out (forward) / g in, y out (inverse)
+    w.rec_bytes = 8.0 * (inverse ? gN + (N + 1) : (N + 1) + gN);
+    // Hahn blocks: coefficients and diagonals in (C_{n,m}, u_m, v_m), values out
+    w.asy_bytes = pt.nblk ? 8.0 * (gN + (N + 1)) + 8.0 * pt.M * (N + 1) + 16.0 * pt.M * gN : 0.0;
+    w.bnd_bytes = 8.0 * ((N + 1) + gN) + (inverse ? 8.0 * gN : 0.0);
+    return w;
+}
 
 cjt_status execute(bool inverse, const std::vector<Inst>& insts, hipStream_t st)
 {
@@ -237,26 +320,49 @@ cjt_status execute(bool inverse, const std::vector<Inst>& insts, hipStream_t st)
         }
         ea.max_jobs = max_jobs;
         ea.max_tasks = max_tasks;
+        Work wk;
+        for (size_t q = 0; q < c.count; ++q) {
+            Work x = work_of(*insts[order[c.first + q]].P, inverse);
+            wk.rec_flops += x.rec_flops;
+            wk.asy_flops += x.asy_flops;
+            wk.bnd_flops += x.bnd_flops;
+            wk.rec_bytes += x.rec_bytes;
+            wk.asy_bytes += x.asy_bytes;
+            wk.bnd_bytes += x.bnd_bytes;
+        }
         if (!inverse) {
-            if ((s = launch_rec_fwd(ea)) != CJT_OK) return s;
+            {
+                ProfScope ps("rec_forward", wk.rec_flops, wk.rec_bytes, st);
+                if ((s = launch_rec_fwd(ea)) != CJT_OK) return s;
+            }
             if (max_jobs > 0) {
                 if ((s = fft_geometry(N, fp32, st, &ea.geom)) != CJT_OK) return s;
+                ProfScope ps(fp32 ? "hahn_blocks_forward_fp32" : "hahn_blocks_forward", wk.asy_flops, wk.asy_bytes, st);
                 if ((s = launch_rdft(ea, Src::FwdAsy, Sink::FwdAsy, fp32)) != CJT_OK) return s;
             }
             if ((s = fft_geometry(N, false, st, &ea.geom)) != CJT_OK) return s;
+            ProfScope ps("dct1_final_forward", wk.bnd_flops, wk.bnd_bytes, st);
             if ((s = launch_rdft(ea, Src::FwdFinal, Sink::FwdFinal, false)) != CJT_OK) return s;
         } else {
             if ((s = fft_geometry(2 * N, false, st, &ea.geom)) != CJT_OK) return s;
-            if ((s = launch_rdft(ea, Src::InvInit, Sink::InvInit, false)) != CJT_OK) return s;
+            {
+                ProfScope ps("dct1_initial_inverse", wk.bnd_flops, wk.bnd_bytes, st);
+                if ((s = launch_rdft(ea, Src::InvInit, Sink::InvInit, false)) != CJT_OK) return s;
+            }
             if (max_jobs > 0) {
                 if ((s = fft_geometry(2 * N, fp32, st, &ea.geom)) != CJT_OK) return s;
+                ProfScope ps(fp32 ? "hahn_blocks_inverse_fp32" : "hahn_blocks_inverse", wk.asy_flops, wk.asy_bytes, st);
                 if ((s = launch_rdft(ea, Src::InvAsy, Sink::InvAsy, fp32)) != CJT_OK) return s;
             } else {
                 dim3 grid((unsigned)((N + 1 + 255) / 256), (unsigned)c.count);
                 hipLaunchKernelGGL(k_zero_out, grid, dim3(256), 0, st, ea.d_desc);
                 CJT_HIP_TRY(hipGetLastError());
             }
-            if ((s = launch_rec_inv(ea)) != CJT_OK) return s;
+            {
+                ProfScope ps("rec_inverse", wk.rec_flops, wk.rec_bytes, st);
+                if ((s = launch_rec_inv(ea)) != CJT_OK) return s;
+            }
+            ProfScope ps("rec_inverse_reduce", 0.0, 16.0 * (double)(N + 1) * c.count, st);
             if ((s = launch_rec_inv_reduce(ea, N)) != CJT_OK) return s;
         }
     }
@@ -348,6 +454,45 @@ const char* cjt_strerror(cjt_status s)
 const char* cjt_last_error(void) { return t_err.c_str(); }
 
 int cjt_version(void) { return 100; }
+
+cjt_status cjt_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return CJT_OK;
+}
+
+cjt_status cjt_profile_collect(cjt_kernel_stat* out, int max, int* n_out)
+{
+    if (!n_out || (max > 0 && !out)) return fail(CJT_EINVAL, "null argument");
+    CJT_HIP_TRY(hipDeviceSynchronize());
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    std::vector<cjt_kernel_stat> agg;
+    cjt_status st = CJT_OK;
+    for (ProfRec& r : g_prof) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) st = fail(CJT_EDEVICE, "event timing failed");
+        size_t i = 0;
+        for (; i < agg.size(); ++i)
+            if (strncmp(agg[i].name, r.name, sizeof(agg[i].name)) == 0) break;
+        if (i == agg.size()) {
+            cjt_kernel_stat k{};
+            strncpy(k.name, r.name, sizeof(k.name) - 1);
+            agg.push_back(k);
+        }
+        agg[i].launches += 1;
+        agg[i].total_ms += ms;
+        agg[i].flops += r.flops;
+        agg[i].bytes += r.bytes;
+        g_ev_pool.push_back(r.a);
+        g_ev_pool.push_back(r.b);
+    }
+    g_prof.clear();
+    int n = (int)std::min<size_t>(agg.size(), (size_t)std::max(max, 0));
+    for (int i = 0; i < n; ++i) out[i] = agg[i];
+    *n_out = n;
+    return st;
+}
 
 cjt_status cjt_plan_describe(int64_t N, double alpha, double beta, int M, unsigned flags, cjt_plan_info* out)
 {

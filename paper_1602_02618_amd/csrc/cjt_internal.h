@@ -19,6 +19,11 @@ struct alignas(2 * sizeof(T)) cx {
     T re, im;
 };
 
+// Four coefficients of one degree of a recurrence, loaded as one record.
+struct alignas(32) d4 {
+    double x, y, z, w;
+};
+
 // A group of grid points handled by one recurrence work-item: points
 // p0 .. p0+np-1, all with the same recurrence form (mode 0 = three-term
 // recurrence, +1 / -1 = the modified form anchored at x0 = +1 / -1) and the same
@@ -49,15 +54,33 @@ struct ExecDesc {
     const double* w;          // [2N+1]     Clenshaw--Curtis weights (inverse)
     const double* s;          // [N+1]      1 / A_n (inverse)
     const RecTask* tasks;     // [ntasks]   recurrence tasks, longest first
-    const double4* rec0;      // [N+2]      three-term coefficients
-    const double4* recp;      // [N+2]      modified form at x0 = +1
-    const double4* recm;      // [N+2]      modified form at x0 = -1
+    const d4* rec0;      // [N+2]      three-term coefficients
+    const d4* recp;      // [N+2]      modified form at x0 = +1
+    const d4* recm;      // [N+2]      modified form at x0 = -1
     const double* in;         // input coefficients (N+1)
     double* out;              // output coefficients (N+1)
     double* p;                // forward: point values (N+1); inverse: g = w .* f (2N+1)
     double* part;             // inverse: recurrence partial sums
     void* tmp;                // FFT intermediates [nblk*M][L] complex
 };
+
+// Read-only views in the constant address space: loads from wave-uniform
+// addresses through these become scalar (s_load) instructions.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p)
+{
+    return (cptr<T>)p;
+}
+
+// Loads through the constant address space, member by member (C++ copies do
+// not bind to address-space-qualified references).
+__device__ __forceinline__ d4 ld(cptr<d4> p) { return d4{p->x, p->y, p->z, p->w}; }
+
+// Wave-uniform copy of an int (the value must already be equal in all lanes).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Geometry of one complex FFT length L (a power of two) on the device.
 struct FftGeom {

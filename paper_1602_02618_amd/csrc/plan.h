@@ -40,13 +40,13 @@ struct Plan {
     cx<double>* uv_i = nullptr;
     double* w = nullptr;
     double* s = nullptr;
-    double4 *f0 = nullptr, *fp = nullptr, *fm = nullptr;
-    double4 *i0 = nullptr, *ip = nullptr, *im = nullptr;
+    d4 *f0 = nullptr, *fp = nullptr, *fm = nullptr;
+    d4 *i0 = nullptr, *ip = nullptr, *im = nullptr;
     RecTask* d_tasks_f = nullptr;
     RecTask* d_tasks_i = nullptr;
 };
 
-constexpr int kRecWidthFwd = 64;        // points per forward recurrence task (one per lane)
+constexpr int kRecWidthFwd = 64 * 4;    // points per forward recurrence task (4 per lane)
 constexpr int kRecWidthInv = 64 * 4;    // points per inverse task (4 per lane)
 
 void compute_partition(int64_t G, int64_t cap, double a, double b, int M, Part* P);

@@ -250,8 +250,8 @@ __device__ inline double rf_pm(double n, double a, double b, int side)
     return side > 0 ? (n + a + 1.0) / (n + 1.0) : -(n + b + 1.0) / (n + 1.0);
 }
 
-__global__ void k_plan_rec(int64_t N, double a, double b, double4* f0, double4* fp, double4* fm, double4* i0,
-                           double4* ip, double4* im)
+__global__ void k_plan_rec(int64_t N, double a, double b, d4* f0, d4* fp, d4* fm, d4* i0,
+                           d4* ip, d4* im)
 {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n > N) return;
@@ -259,17 +259,17 @@ __global__ void k_plan_rec(int64_t N, double a, double b, double4* f0, double4* 
     double A, B, C, A1, B1, C1;
     rec_ABC(dn, a, b, &A, &B, &C);
     rec_ABC(dn + 1.0, a, b, &A1, &B1, &C1);
-    f0[n] = make_double4(A, B, C1, 0.0);
-    i0[n] = make_double4(A, B, C, 0.0);
+    f0[n] = d4{A, B, C1, 0.0};
+    i0[n] = d4{A, B, C, 0.0};
     const double rbp1 = rb_pm(dn + 1.0, a, b, +1), rbm1 = rb_pm(dn + 1.0, a, b, -1);
     const double rbip = n >= 1 ? 1.0 / rb_pm(dn, a, b, +1) : 0.0;
     const double rbim = n >= 1 ? 1.0 / rb_pm(dn, a, b, -1) : 0.0;
-    fp[n] = make_double4(A, C1 * rbp1, rbip, 0.0);
-    fm[n] = make_double4(A, C1 * rbm1, rbim, 0.0);
+    fp[n] = d4{A, C1 * rbp1, rbip, 0.0};
+    fm[n] = d4{A, C1 * rbm1, rbim, 0.0};
     const double hp = n >= 1 ? C / rf_pm(dn - 1.0, a, b, +1) : 0.0;
     const double hm = n >= 1 ? C / rf_pm(dn - 1.0, a, b, -1) : 0.0;
-    ip[n] = make_double4(A, hp, rf_pm(dn, a, b, +1), 0.0);
-    im[n] = make_double4(A, hm, rf_pm(dn, a, b, -1), 0.0);
+    ip[n] = d4{A, hp, rf_pm(dn, a, b, +1), 0.0};
+    im[n] = d4{A, hm, rf_pm(dn, a, b, -1), 0.0};
 }
 
 // C_{n,m}, m < M, for n >= nlo (zero below): eq. Cnmabasy at m = 0, then the
@@ -386,7 +386,7 @@ cjt_status build_plan_device(Plan* P, hipStream_t st)
     const size_t oUVi = take(sizeof(cx<double>) * (size_t)P->inv.M * ni);
     const size_t oW = take(sizeof(double) * ni);
     const size_t oS = take(sizeof(double) * nf);
-    const size_t oR = take(sizeof(double4) * 6 * (size_t)nf);
+    const size_t oR = take(sizeof(d4) * 6 * (size_t)nf);
     const size_t oTf = take(sizeof(RecTask) * std::max<size_t>(1, P->tasks_f.size()));
     const size_t oTi = take(sizeof(RecTask) * std::max<size_t>(1, P->tasks_i.size()));
     const size_t oMu = take(sizeof(double) * ni);
@@ -398,7 +398,7 @@ cjt_status build_plan_device(Plan* P, hipStream_t st)
     P->uv_i = (cx<double>*)(base + oUVi);
     P->w = (double*)(base + oW);
     P->s = (double*)(base + oS);
-    double4* R = (double4*)(base + oR);
+    d4* R = (d4*)(base + oR);
     P->f0 = R;
     P->fp = R + nf;
     P->fm = R + 2 * nf;

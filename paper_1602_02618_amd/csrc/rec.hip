@@ -29,50 +29,122 @@ constexpr int kChunk = 16;  // degrees per LDS reduction round
 
 // ------------------------------------------------------------------ forward
 
+// Each lane carries kPPTF points of the task (up to 64*kPPTF points, one
+// recurrence per point); coefficients are loaded once per degree for all of
+// them through the scalar cache, kUnroll degrees at a time.
+constexpr int kPPTF = 4;
+constexpr int kUnroll = 8;
+
 __global__ void __launch_bounds__(64) k_rec_fwd(const ExecDesc* __restrict__ descs)
 {
     const ExecDesc& d = descs[blockIdx.x];
     const int task = blockIdx.y;
     if (task >= d.ntasks) return;
-    const RecTask tk = d.tasks[task];
+    cptr<RecTask> tp = as_const(d.tasks) + task;
+    const int p0 = uniform(tp->p0), np = uniform(tp->np), mode = uniform(tp->mode), cut = uniform(tp->cut);
     const int lane = threadIdx.x;
-    const bool active = lane < tk.np;
-    const int64_t i = tk.p0 + (active ? lane : 0);
     const int64_t N = d.N;
-    const double* __restrict__ c = d.in;
-    const int cut = tk.cut;
-    double res = 0.0;
-    if (tk.mode == 0) {
-        double s, x;
-        sincospi((double)i / (double)N, &s, &x);
-        const double4* __restrict__ co = d.rec0;  // (A_n, B_n, C_{n+1})
-        double u1 = 0.0, u2 = 0.0;
-        for (int n = cut - 1; n >= 0; --n) {
-            const double4 q = co[n];
-            const double u0 = fma(fma(q.x, x, q.y), u1, fma(-q.z, u2, c[n]));
-            u2 = u1;
-            u1 = u0;
+    cptr<double> c = as_const(d.in);
+    double res[kPPTF];
+    if (mode == 0) {
+        double x[kPPTF], u1[kPPTF], u2[kPPTF];
+#pragma unroll
+        for (int q = 0; q < kPPTF; ++q) {
+            const int idx = lane + 64 * q;
+            const int64_t i = p0 + (idx < np ? idx : 0);
+            double s;
+            sincospi((double)i / (double)N, &s, &x[q]);
+            u1[q] = 0.0;
+            u2[q] = 0.0;
         }
-        res = u1;
+        cptr<d4> co = as_const(d.rec0);  // (A_n, B_n, C_{n+1})
+        int n = cut - 1;
+        for (; n >= kUnroll - 1; n -= kUnroll) {
+            d4 qv[kUnroll];
+            double cv[kUnroll];
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) {
+                qv[k] = ld(co + (n - k));
+                cv[k] = c[n - k];
+            }
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) {
+#pragma unroll
+                for (int q = 0; q < kPPTF; ++q) {
+                    const double u0 = fma(fma(qv[k].x, x[q], qv[k].y), u1[q], fma(-qv[k].z, u2[q], cv[k]));
+                    u2[q] = u1[q];
+                    u1[q] = u0;
+                }
+            }
+        }
+        for (; n >= 0; --n) {
+            const d4 qn = ld(co + n);
+            const double cn = c[n];
+#pragma unroll
+            for (int q = 0; q < kPPTF; ++q) {
+                const double u0 = fma(fma(qn.x, x[q], qn.y), u1[q], fma(-qn.z, u2[q], cn));
+                u2[q] = u1[q];
+                u1[q] = u0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kPPTF; ++q) res[q] = u1[q];
     } else {
-        double sh, ch;
-        sincospi((double)i / (double)(2 * N), &sh, &ch);
-        const double dx = tk.mode > 0 ? -2.0 * sh * sh : 2.0 * ch * ch;
-        const double4* __restrict__ co = tk.mode > 0 ? d.recp : d.recm;  // (A_n, C_{n+1} r_{n+1}, 1/r_n)
-        double u = 0.0, D = 0.0;
-        for (int n = cut - 1; n >= 1; --n) {
-            const double4 q = co[n];
-            const double Dn = fma(q.x * dx, u, fma(q.y, D, c[n]));
-            u = fma(u, q.z, Dn);
-            D = Dn;
+        double dx[kPPTF], u[kPPTF], D[kPPTF];
+#pragma unroll
+        for (int q = 0; q < kPPTF; ++q) {
+            const int idx = lane + 64 * q;
+            const int64_t i = p0 + (idx < np ? idx : 0);
+            double sh, ch;
+            sincospi((double)i / (double)(2 * N), &sh, &ch);
+            dx[q] = mode > 0 ? -2.0 * sh * sh : 2.0 * ch * ch;
+            u[q] = 0.0;
+            D[q] = 0.0;
+        }
+        cptr<d4> co = as_const(mode > 0 ? d.recp : d.recm);  // (A_n, C_{n+1} r_{n+1}, 1/r_n)
+        int n = cut - 1;
+        for (; n >= kUnroll; n -= kUnroll) {
+            d4 qv[kUnroll];
+            double cv[kUnroll];
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) {
+                qv[k] = ld(co + (n - k));
+                cv[k] = c[n - k];
+            }
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) {
+#pragma unroll
+                for (int q = 0; q < kPPTF; ++q) {
+                    const double Dn = fma(qv[k].x * dx[q], u[q], fma(qv[k].y, D[q], cv[k]));
+                    u[q] = fma(u[q], qv[k].z, Dn);
+                    D[q] = Dn;
+                }
+            }
+        }
+        for (; n >= 1; --n) {
+            const d4 qn = ld(co + n);
+            const double cn = c[n];
+#pragma unroll
+            for (int q = 0; q < kPPTF; ++q) {
+                const double Dn = fma(qn.x * dx[q], u[q], fma(qn.y, D[q], cn));
+                u[q] = fma(u[q], qn.z, Dn);
+                D[q] = Dn;
+            }
         }
         if (cut >= 1) {
-            const double4 q = co[0];
-            D = fma(q.x * dx, u, fma(q.y, D, c[0]));
+            const d4 qn = ld(co);
+            const double cn = c[0];
+#pragma unroll
+            for (int q = 0; q < kPPTF; ++q) D[q] = fma(qn.x * dx[q], u[q], fma(qn.y, D[q], cn));
         }
-        res = D;
+#pragma unroll
+        for (int q = 0; q < kPPTF; ++q) res[q] = D[q];
     }
-    if (active) d.p[i] = res;
+#pragma unroll
+    for (int q = 0; q < kPPTF; ++q) {
+        const int idx = lane + 64 * q;
+        if (idx < np) d.p[p0 + idx] = res[q];
+    }
 }
 
 cjt_status launch_rec_fwd(const EngineArgs& a)
@@ -92,43 +164,45 @@ __global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ des
     const ExecDesc& d = descs[blockIdx.x];
     const int task = blockIdx.y;
     if (task >= d.ntasks) return;
-    const RecTask tk = d.tasks[task];
+    cptr<RecTask> tp = as_const(d.tasks) + task;
+    const int p0 = uniform(tp->p0), np = uniform(tp->np), mode = uniform(tp->mode), cut = uniform(tp->cut);
+    const int64_t off = tp->off;
     const int lane = threadIdx.x;
     const int64_t G = d.G;
-    const int cut = tk.cut;
-    double* __restrict__ part = d.part + tk.off;
+    double* __restrict__ part = d.part + off;
 
     double pv[kPPT], ev[kPPT], xv[kPPT];
 #pragma unroll
     for (int q = 0; q < kPPT; ++q) {
         const int idx = lane + 64 * q;
-        const bool act = idx < tk.np;
-        const int64_t j = tk.p0 + (act ? idx : 0);
+        const bool act = idx < np;
+        const int64_t j = p0 + (act ? idx : 0);
         const double g = act ? d.p[j] : 0.0;
         pv[q] = g;      // pi_0 = g_j (scaled recurrence)
         ev[q] = 0.0;    // e_0 = 0 (modified) / P_{-1} = 0 (three-term)
-        if (tk.mode == 0) {
+        if (mode == 0) {
             double s, x;
             sincospi((double)j / (double)G, &s, &x);
             xv[q] = x;
         } else {
             double sh, ch;
             sincospi((double)j / (double)(2 * G), &sh, &ch);
-            xv[q] = tk.mode > 0 ? -2.0 * sh * sh : 2.0 * ch * ch;
+            xv[q] = mode > 0 ? -2.0 * sh * sh : 2.0 * ch * ch;
         }
     }
-    const double4* __restrict__ co = tk.mode == 0 ? d.rec0 : (tk.mode > 0 ? d.recp : d.recm);
+    cptr<d4> co = as_const(mode == 0 ? d.rec0 : (mode > 0 ? d.recp : d.recm));
     const int dd = lane >> 2, qq = lane & 3;  // reduction: degree dd of the chunk, quarter qq of the 64 lanes
     for (int n0 = 0; n0 < cut; n0 += kChunk) {
         const int nend = min(kChunk, cut - n0);
+#pragma unroll 4
         for (int t = 0; t < nend; ++t) {
             const int n = n0 + t;
             double v = 0.0;
 #pragma unroll
             for (int q = 0; q < kPPT; ++q) v += pv[q];
             red[t][lane] = v;
-            const double4 cf = co[n];
-            if (tk.mode == 0) {
+            const d4 cf = ld(co + n);
+            if (mode == 0) {
                 // rec0 holds (A_n, B_n, C_n) for the three-term recurrence
 #pragma unroll
                 for (int q = 0; q < kPPT; ++q) {
@@ -176,10 +250,11 @@ __global__ void __launch_bounds__(256) k_rec_inv_reduce(const ExecDesc* __restri
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n > d.N) return;
     double acc = 0.0;
+    cptr<RecTask> tasks = as_const(d.tasks);
     for (int t = 0; t < d.ntasks; ++t) {
-        const RecTask tk = d.tasks[t];
-        if (tk.cut <= n) break;
-        acc += d.part[tk.off + n];
+        const int cut = tasks[t].cut;
+        if (cut <= n) break;
+        acc += d.part[tasks[t].off + n];
     }
     d.out[n] = d.s[n] * (d.out[n] + acc);
 }
