@@ -97,6 +97,8 @@ namespace {
 struct Workspace {
     void* dev = nullptr;
     size_t bytes = 0;
+    hipStream_t aux = nullptr;    // second stream for the recurrence kernels (default priority)
+    hipEvent_t fork = nullptr, join = nullptr;
     ExecDesc* d_desc = nullptr;
     size_t desc_cap = 0;
     ExecDesc* h_desc = nullptr;   // pinned staging
@@ -146,6 +148,9 @@ cjt_status ws_reserve(Workspace& w, size_t bytes, size_t ndesc, hipStream_t st)
         w.desc_cap = cap;
     }
     if (!w.copied) CJT_HIP_TRY(hipEventCreateWithFlags(&w.copied, hipEventDisableTiming));
+    if (!w.aux) CJT_HIP_TRY(hipStreamCreateWithFlags(&w.aux, hipStreamNonBlocking));
+    if (!w.fork) CJT_HIP_TRY(hipEventCreateWithFlags(&w.fork, hipEventDisableTiming));
+    if (!w.join) CJT_HIP_TRY(hipEventCreateWithFlags(&w.join, hipEventDisableTiming));
     return CJT_OK;
 }
 
@@ -163,9 +168,10 @@ struct Inst {
     double* out;
 };
 
-// Per-instance workspace needs (bytes), split by use.
+// Per-instance workspace needs (bytes), split by use: p, p2 and part live for
+// the whole call (all instances at once), tmp only for the instance's chunk.
 struct Need {
-    size_t p, part, tmp;
+    size_t p, p2, part, tmp;
 };
 
 Need need_of(const Plan& P, bool inverse, bool fp32)
@@ -175,6 +181,7 @@ Need need_of(const Plan& P, bool inverse, bool fp32)
     const int64_t L = inverse ? 2 * P.N : P.N;
     Need n;
     n.p = sizeof(double) * (size_t)(inverse ? 2 * P.N + 1 : P.N + 1);
+    n.p2 = inverse ? 0 : sizeof(double) * (size_t)(P.N + 1);
     n.part = inverse ? sizeof(double) * (size_t)std::max<int64_t>(1, P.part_total_i) : 0;
     const int64_t jobs = (int64_t)pt.nblk * pt.M;
     const bool two_pass = L > kSingleMax;
@@ -233,123 +240,164 @@ cjt_status execute(bool inverse, const std::vector<Inst>& insts, hipStream_t st)
     std::lock_guard<std::mutex> lk(g_ws_mu);
     Workspace& ws = g_ws[{dev, st}];
 
-    // chunks: runs of equal N whose workspace fits the limit
+    // chunks: runs of equal N whose FFT intermediates fit the limit
     struct Chunk {
         size_t first, count;
-        size_t bytes;
+        size_t tmp_bytes;
     };
     std::vector<Chunk> chunks;
-    size_t max_bytes = 0;
+    size_t max_tmp = 0, persist = 0;
     for (size_t i = 0; i < order.size();) {
         const int64_t N = insts[order[i]].P->N;
         Chunk c{i, 0, 0};
         while (i < order.size() && insts[order[i]].P->N == N) {
             Need nd = need_of(*insts[order[i]].P, inverse, fp32);
-            size_t add = a256(nd.p) + a256(nd.part) + a256(nd.tmp);
-            if (c.count > 0 && c.bytes + add > ws_limit()) break;
-            c.bytes += add;
+            if (c.count > 0 && c.tmp_bytes + a256(nd.tmp) > ws_limit()) break;
+            c.tmp_bytes += a256(nd.tmp);
+            persist += a256(nd.p) + a256(nd.p2) + a256(nd.part);
             ++c.count;
             ++i;
         }
-        max_bytes = std::max(max_bytes, c.bytes);
+        max_tmp = std::max(max_tmp, c.tmp_bytes);
         chunks.push_back(c);
     }
-    cjt_status s = ws_reserve(ws, max_bytes, insts.size(), st);
+    cjt_status s = ws_reserve(ws, persist + max_tmp, insts.size(), st);
     if (s != CJT_OK) return s;
 
     // descriptors for every instance, in chunk order, copied once
-    for (const Chunk& c : chunks) {
+    {
         char* base = (char*)ws.dev;
-        size_t off = 0;
-        for (size_t q = 0; q < c.count; ++q) {
-            const size_t idx = c.first + q;
-            const Inst& x = insts[order[idx]];
-            const Plan& P = *x.P;
-            const Part& pt = inverse ? P.inv : P.fwd;
-            Need nd = need_of(P, inverse, fp32);
-            ExecDesc d{};
-            d.N = P.N;
-            d.G = inverse ? 2 * P.N : P.N;
-            d.alpha = P.alpha;
-            d.beta = P.beta;
-            d.M = pt.M;
-            d.nblk = pt.nblk;
-            for (int k = 0; k < pt.nblk; ++k) {
-                d.deg_lo[k] = pt.deg_lo[k];
-                d.deg_hi[k] = pt.deg_hi[k];
-                d.win_lo[k] = pt.win_lo[k];
-                d.win_hi[k] = pt.win_hi[k];
+        size_t poff = 0;                 // persistent region [0, persist)
+        for (const Chunk& c : chunks) {
+            size_t toff = persist;       // chunk region [persist, persist + max_tmp)
+            for (size_t q = 0; q < c.count; ++q) {
+                const size_t idx = c.first + q;
+                const Inst& x = insts[order[idx]];
+                const Plan& P = *x.P;
+                const Part& pt = inverse ? P.inv : P.fwd;
+                Need nd = need_of(P, inverse, fp32);
+                ExecDesc d{};
+                d.N = P.N;
+                d.G = inverse ? 2 * P.N : P.N;
+                d.alpha = P.alpha;
+                d.beta = P.beta;
+                d.M = pt.M;
+                d.nblk = pt.nblk;
+                for (int k = 0; k < pt.nblk; ++k) {
+                    d.deg_lo[k] = pt.deg_lo[k];
+                    d.deg_hi[k] = pt.deg_hi[k];
+                    d.win_lo[k] = pt.win_lo[k];
+                    d.win_hi[k] = pt.win_hi[k];
+                }
+                d.C = P.C;
+                d.uv = inverse ? P.uv_i : P.uv_f;
+                d.w = P.w;
+                d.s = P.s;
+                d.tasks = inverse ? P.d_tasks_i : P.d_tasks_f;
+                d.ntasks = (int32_t)(inverse ? P.tasks_i.size() : P.tasks_f.size());
+                d.rec0 = inverse ? P.i0 : P.f0;
+                d.recp = inverse ? P.ip : P.fp;
+                d.recm = inverse ? P.im : P.fm;
+                d.in = x.in;
+                d.out = x.out;
+                d.p = (double*)(base + poff);
+                poff += a256(nd.p);
+                d.p2 = nd.p2 ? (double*)(base + poff) : nullptr;
+                poff += a256(nd.p2);
+                d.part = nd.part ? (double*)(base + poff) : nullptr;
+                poff += a256(nd.part);
+                d.tmp = nd.tmp ? (void*)(base + toff) : nullptr;
+                toff += a256(nd.tmp);
+                ws.h_desc[idx] = d;
             }
-            d.C = P.C;
-            d.uv = inverse ? P.uv_i : P.uv_f;
-            d.w = P.w;
-            d.s = P.s;
-            d.tasks = inverse ? P.d_tasks_i : P.d_tasks_f;
-            d.ntasks = (int32_t)(inverse ? P.tasks_i.size() : P.tasks_f.size());
-            d.rec0 = inverse ? P.i0 : P.f0;
-            d.recp = inverse ? P.ip : P.fp;
-            d.recm = inverse ? P.im : P.fm;
-            d.in = x.in;
-            d.out = x.out;
-            d.p = (double*)(base + off);
-            off += a256(nd.p);
-            d.part = nd.part ? (double*)(base + off) : nullptr;
-            off += a256(nd.part);
-            d.tmp = nd.tmp ? (void*)(base + off) : nullptr;
-            off += a256(nd.tmp);
-            ws.h_desc[idx] = d;
         }
     }
     CJT_HIP_TRY(hipMemcpyAsync(ws.d_desc, ws.h_desc, sizeof(ExecDesc) * insts.size(), hipMemcpyHostToDevice, st));
     CJT_HIP_TRY(hipEventRecord(ws.copied, st));
     ws.pending = true;
 
-    for (const Chunk& c : chunks) {
-        const Plan& P0 = *insts[order[c.first]].P;
-        const int64_t N = P0.N;
+    // whole-call arguments for the recurrence kernels (any mix of N)
+    EngineArgs all{};
+    all.d_desc = ws.d_desc;
+    all.count = (int)insts.size();
+    all.stream = ws.aux;
+    int64_t maxN = 0;
+    Work wall;
+    for (const Inst& x : insts) {
+        const Plan& P = *x.P;
+        all.max_tasks = std::max(all.max_tasks, (int)(inverse ? P.tasks_i.size() : P.tasks_f.size()));
+        maxN = std::max(maxN, P.N);
+        Work w = work_of(P, inverse);
+        wall.rec_flops += w.rec_flops;
+        wall.rec_bytes += w.rec_bytes;
+    }
+    auto chunk_args = [&](const Chunk& c, Work* wk) {
         EngineArgs ea{};
         ea.d_desc = ws.d_desc + c.first;
         ea.count = (int)c.count;
         ea.stream = st;
-        int max_jobs = 0, max_tasks = 0;
         for (size_t q = 0; q < c.count; ++q) {
             const Plan& P = *insts[order[c.first + q]].P;
             const Part& pt = inverse ? P.inv : P.fwd;
-            max_jobs = std::max(max_jobs, pt.nblk * pt.M);
-            max_tasks = std::max(max_tasks, (int)(inverse ? P.tasks_i.size() : P.tasks_f.size()));
+            ea.max_jobs = std::max(ea.max_jobs, pt.nblk * pt.M);
+            Work x = work_of(P, inverse);
+            wk->asy_flops += x.asy_flops;
+            wk->bnd_flops += x.bnd_flops;
+            wk->asy_bytes += x.asy_bytes;
+            wk->bnd_bytes += x.bnd_bytes;
         }
-        ea.max_jobs = max_jobs;
-        ea.max_tasks = max_tasks;
-        Work wk;
-        for (size_t q = 0; q < c.count; ++q) {
-            Work x = work_of(*insts[order[c.first + q]].P, inverse);
-            wk.rec_flops += x.rec_flops;
-            wk.asy_flops += x.asy_flops;
-            wk.bnd_flops += x.bnd_flops;
-            wk.rec_bytes += x.rec_bytes;
-            wk.asy_bytes += x.asy_bytes;
-            wk.bnd_bytes += x.bnd_bytes;
+        return ea;
+    };
+
+    if (!inverse) {
+        // recurrence part on the auxiliary stream, Hahn blocks on the caller's, then the final DCT-I
+        CJT_HIP_TRY(hipEventRecord(ws.fork, st));
+        CJT_HIP_TRY(hipStreamWaitEvent(ws.aux, ws.fork, 0));
+        {
+            ProfScope ps("rec_forward", wall.rec_flops, wall.rec_bytes, ws.aux);
+            if ((s = launch_rec_fwd(all)) != CJT_OK) return s;
         }
-        if (!inverse) {
-            {
-                ProfScope ps("rec_forward", wk.rec_flops, wk.rec_bytes, st);
-                if ((s = launch_rec_fwd(ea)) != CJT_OK) return s;
-            }
-            if (max_jobs > 0) {
+        CJT_HIP_TRY(hipEventRecord(ws.join, ws.aux));
+        for (const Chunk& c : chunks) {
+            Work wk;
+            EngineArgs ea = chunk_args(c, &wk);
+            const int64_t N = insts[order[c.first]].P->N;
+            if (ea.max_jobs > 0) {
                 if ((s = fft_geometry(N, fp32, st, &ea.geom)) != CJT_OK) return s;
                 ProfScope ps(fp32 ? "hahn_blocks_forward_fp32" : "hahn_blocks_forward", wk.asy_flops, wk.asy_bytes, st);
                 if ((s = launch_rdft(ea, Src::FwdAsy, Sink::FwdAsy, fp32)) != CJT_OK) return s;
             }
+        }
+        CJT_HIP_TRY(hipStreamWaitEvent(st, ws.join, 0));
+        for (const Chunk& c : chunks) {
+            Work wk;
+            EngineArgs ea = chunk_args(c, &wk);
+            const int64_t N = insts[order[c.first]].P->N;
             if ((s = fft_geometry(N, false, st, &ea.geom)) != CJT_OK) return s;
             ProfScope ps("dct1_final_forward", wk.bnd_flops, wk.bnd_bytes, st);
             if ((s = launch_rdft(ea, Src::FwdFinal, Sink::FwdFinal, false)) != CJT_OK) return s;
-        } else {
+        }
+    } else {
+        for (const Chunk& c : chunks) {
+            Work wk;
+            EngineArgs ea = chunk_args(c, &wk);
+            const int64_t N = insts[order[c.first]].P->N;
             if ((s = fft_geometry(2 * N, false, st, &ea.geom)) != CJT_OK) return s;
-            {
-                ProfScope ps("dct1_initial_inverse", wk.bnd_flops, wk.bnd_bytes, st);
-                if ((s = launch_rdft(ea, Src::InvInit, Sink::InvInit, false)) != CJT_OK) return s;
-            }
-            if (max_jobs > 0) {
+            ProfScope ps("dct1_initial_inverse", wk.bnd_flops, wk.bnd_bytes, st);
+            if ((s = launch_rdft(ea, Src::InvInit, Sink::InvInit, false)) != CJT_OK) return s;
+        }
+        CJT_HIP_TRY(hipEventRecord(ws.fork, st));
+        CJT_HIP_TRY(hipStreamWaitEvent(ws.aux, ws.fork, 0));
+        {
+            ProfScope ps("rec_inverse", wall.rec_flops, wall.rec_bytes, ws.aux);
+            if ((s = launch_rec_inv(all)) != CJT_OK) return s;
+        }
+        CJT_HIP_TRY(hipEventRecord(ws.join, ws.aux));
+        for (const Chunk& c : chunks) {
+            Work wk;
+            EngineArgs ea = chunk_args(c, &wk);
+            const int64_t N = insts[order[c.first]].P->N;
+            if (ea.max_jobs > 0) {
                 if ((s = fft_geometry(2 * N, fp32, st, &ea.geom)) != CJT_OK) return s;
                 ProfScope ps(fp32 ? "hahn_blocks_inverse_fp32" : "hahn_blocks_inverse", wk.asy_flops, wk.asy_bytes, st);
                 if ((s = launch_rdft(ea, Src::InvAsy, Sink::InvAsy, fp32)) != CJT_OK) return s;
@@ -358,13 +406,11 @@ cjt_status execute(bool inverse, const std::vector<Inst>& insts, hipStream_t st)
                 hipLaunchKernelGGL(k_zero_out, grid, dim3(256), 0, st, ea.d_desc);
                 CJT_HIP_TRY(hipGetLastError());
             }
-            {
-                ProfScope ps("rec_inverse", wk.rec_flops, wk.rec_bytes, st);
-                if ((s = launch_rec_inv(ea)) != CJT_OK) return s;
-            }
-            ProfScope ps("rec_inverse_reduce", 0.0, 16.0 * (double)(N + 1) * c.count, st);
-            if ((s = launch_rec_inv_reduce(ea, N)) != CJT_OK) return s;
         }
+        CJT_HIP_TRY(hipStreamWaitEvent(st, ws.join, 0));
+        all.stream = st;
+        ProfScope ps("rec_inverse_reduce", 0.0, 16.0 * (double)(maxN + 1) * all.count, st);
+        if ((s = launch_rec_inv_reduce(all, maxN)) != CJT_OK) return s;
     }
     return CJT_OK;
 }

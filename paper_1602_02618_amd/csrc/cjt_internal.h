@@ -59,7 +59,8 @@ struct ExecDesc {
     const d4* recm;      // [N+2]      modified form at x0 = -1
     const double* in;         // input coefficients (N+1)
     double* out;              // output coefficients (N+1)
-    double* p;                // forward: point values (N+1); inverse: g = w .* f (2N+1)
+    double* p;                // forward: recurrence part of the point values (N+1); inverse: g = w .* f (2N+1)
+    double* p2;               // forward: Hahn-block part of the point values (N+1)
     double* part;             // inverse: recurrence partial sums
     void* tmp;                // FFT intermediates [nblk*M][L] complex
 };

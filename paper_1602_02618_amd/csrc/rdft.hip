@@ -82,11 +82,13 @@ struct Source<Src::InvAsy> {
 template <>
 struct Source<Src::FwdFinal> {
     __device__ static bool valid(const ExecDesc&, int job) { return job == 0; }
+    // p = recurrence part + Hahn-block part (the latter only if the plan has blocks)
+    __device__ static double pv(const ExecDesc& d, int64_t j) { return d.nblk > 0 ? d.p[j] + d.p2[j] : d.p[j]; }
     __device__ static cx<double> load(const ExecDesc& d, int, int64_t t)
     {
         const int64_t N = d.N, j0 = 2 * t, j1 = j0 + 1;
-        double x0 = j0 <= N ? d.p[j0] * ((j0 == 0 || j0 == N) ? 0.5 : 1.0) : 0.0;
-        double x1 = j1 <= N ? d.p[j1] * ((j1 == N) ? 0.5 : 1.0) : 0.0;
+        double x0 = j0 <= N ? pv(d, j0) * ((j0 == 0 || j0 == N) ? 0.5 : 1.0) : 0.0;
+        double x1 = j1 <= N ? pv(d, j1) * ((j1 == N) ? 0.5 : 1.0) : 0.0;
         return {x0, x1};
     }
 };
@@ -133,8 +135,9 @@ struct Target<Sink::FwdAsy> {
         const cx<double> uv = d.uv[(int64_t)m * (d.G + 1) + i];
         acc[slot] = fma(uv.re, X.re, fma(uv.im, X.im, acc[slot]));
     }
-    __device__ static void finish(const ExecDesc& d, int64_t i, double v) { d.p[i] += v; }
-    static constexpr bool kNeedsAll = false;  // only indices inside some window matter
+    // every point is written (zero outside the windows); the final DCT-I adds
+    // the recurrence part
+    __device__ static void finish(const ExecDesc& d, int64_t i, double v) { d.p2[i] = v; }
 };
 
 template <>

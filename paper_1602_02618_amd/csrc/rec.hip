@@ -25,18 +25,58 @@
 namespace cjt {
 
 constexpr int kPPT = 4;     // points per thread, inverse
-constexpr int kChunk = 16;  // degrees per LDS reduction round
+constexpr int kChunk = 16;  // degrees per LDS reduction round (divides kBlk)
 
 // ------------------------------------------------------------------ forward
 
 // Each lane carries kPPTF points of the task (up to 64*kPPTF points, one
-// recurrence per point); coefficients are loaded once per degree for all of
-// them through the scalar cache, kUnroll degrees at a time.
+// recurrence per point).  The per-degree coefficients (a d4 record and c_n)
+// are staged through LDS in blocks of kBlk degrees with coalesced vector
+// loads; the loads of the next block are issued before the current block is
+// consumed, so the serial chain never waits on memory latency.
 constexpr int kPPTF = 4;
-constexpr int kUnroll = 8;
+constexpr int kBlk = 128;
+
+struct Stage {
+    d4 co[kBlk];
+    double c[kBlk];
+};
+
+// Global -> registers for degrees [n0, n0 + kBlk) (clipped to [lo, hi)): lane l
+// takes degrees n0 + l and n0 + l + 64.
+struct StageRegs {
+    d4 co[2];
+    double c[2];
+};
+
+__device__ __forceinline__ void stage_load(StageRegs& r, const d4* __restrict__ co, const double* __restrict__ c,
+                                           int n0, int lo, int hi, int lane)
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int n = n0 + lane + 64 * h;
+        if (n >= lo && n < hi) {
+            r.co[h] = co[n];
+            r.c[h] = c ? c[n] : 0.0;
+        } else {
+            r.co[h] = d4{0.0, 0.0, 0.0, 0.0};
+            r.c[h] = 0.0;
+        }
+    }
+}
+
+__device__ __forceinline__ void stage_store(Stage& st, const StageRegs& r, int lane)
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        st.co[lane + 64 * h] = r.co[h];
+        st.c[lane + 64 * h] = r.c[h];
+    }
+}
 
 __global__ void __launch_bounds__(64) k_rec_fwd(const ExecDesc* __restrict__ descs)
 {
+    __shared__ Stage stg[2];
     const ExecDesc& d = descs[blockIdx.x];
     const int task = blockIdx.y;
     if (task >= d.ntasks) return;
@@ -44,106 +84,73 @@ __global__ void __launch_bounds__(64) k_rec_fwd(const ExecDesc* __restrict__ des
     const int p0 = uniform(tp->p0), np = uniform(tp->np), mode = uniform(tp->mode), cut = uniform(tp->cut);
     const int lane = threadIdx.x;
     const int64_t N = d.N;
-    cptr<double> c = as_const(d.in);
-    double res[kPPTF];
-    if (mode == 0) {
-        double x[kPPTF], u1[kPPTF], u2[kPPTF];
+    const double* __restrict__ c = d.in;
+    const d4* __restrict__ co = mode == 0 ? d.rec0 : (mode > 0 ? d.recp : d.recm);
+    // plain: (A_n, B_n, C_{n+1});  modified: (A_n, C_{n+1} r_{n+1}, 1/r_n)
+    double xv[kPPTF], s1[kPPTF], s2[kPPTF];
 #pragma unroll
-        for (int q = 0; q < kPPTF; ++q) {
-            const int idx = lane + 64 * q;
-            const int64_t i = p0 + (idx < np ? idx : 0);
-            double s;
-            sincospi((double)i / (double)N, &s, &x[q]);
-            u1[q] = 0.0;
-            u2[q] = 0.0;
-        }
-        cptr<d4> co = as_const(d.rec0);  // (A_n, B_n, C_{n+1})
-        int n = cut - 1;
-        for (; n >= kUnroll - 1; n -= kUnroll) {
-            d4 qv[kUnroll];
-            double cv[kUnroll];
-#pragma unroll
-            for (int k = 0; k < kUnroll; ++k) {
-                qv[k] = ld(co + (n - k));
-                cv[k] = c[n - k];
-            }
-#pragma unroll
-            for (int k = 0; k < kUnroll; ++k) {
-#pragma unroll
-                for (int q = 0; q < kPPTF; ++q) {
-                    const double u0 = fma(fma(qv[k].x, x[q], qv[k].y), u1[q], fma(-qv[k].z, u2[q], cv[k]));
-                    u2[q] = u1[q];
-                    u1[q] = u0;
-                }
-            }
-        }
-        for (; n >= 0; --n) {
-            const d4 qn = ld(co + n);
-            const double cn = c[n];
-#pragma unroll
-            for (int q = 0; q < kPPTF; ++q) {
-                const double u0 = fma(fma(qn.x, x[q], qn.y), u1[q], fma(-qn.z, u2[q], cn));
-                u2[q] = u1[q];
-                u1[q] = u0;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < kPPTF; ++q) res[q] = u1[q];
-    } else {
-        double dx[kPPTF], u[kPPTF], D[kPPTF];
-#pragma unroll
-        for (int q = 0; q < kPPTF; ++q) {
-            const int idx = lane + 64 * q;
-            const int64_t i = p0 + (idx < np ? idx : 0);
+    for (int q = 0; q < kPPTF; ++q) {
+        const int idx = lane + 64 * q;
+        const int64_t i = p0 + (idx < np ? idx : 0);
+        if (mode == 0) {
+            double sn;
+            sincospi((double)i / (double)N, &sn, &xv[q]);
+        } else {
             double sh, ch;
             sincospi((double)i / (double)(2 * N), &sh, &ch);
-            dx[q] = mode > 0 ? -2.0 * sh * sh : 2.0 * ch * ch;
-            u[q] = 0.0;
-            D[q] = 0.0;
+            xv[q] = mode > 0 ? -2.0 * sh * sh : 2.0 * ch * ch;
         }
-        cptr<d4> co = as_const(mode > 0 ? d.recp : d.recm);  // (A_n, C_{n+1} r_{n+1}, 1/r_n)
-        int n = cut - 1;
-        for (; n >= kUnroll; n -= kUnroll) {
-            d4 qv[kUnroll];
-            double cv[kUnroll];
-#pragma unroll
-            for (int k = 0; k < kUnroll; ++k) {
-                qv[k] = ld(co + (n - k));
-                cv[k] = c[n - k];
-            }
-#pragma unroll
-            for (int k = 0; k < kUnroll; ++k) {
+        s1[q] = 0.0;  // plain: u_{n+1};  modified: u_{n+1}
+        s2[q] = 0.0;  // plain: u_{n+2};  modified: D_{n+1}
+    }
+    // blocks cover [b0, b0 + kBlk) with b0 descending from the top
+    const int nblk = (cut + kBlk - 1) / kBlk;
+    StageRegs rg;
+    int buf = 0;
+    if (nblk > 0) {
+        stage_load(rg, co, c, (nblk - 1) * kBlk, 0, cut, lane);
+        stage_store(stg[0], rg, lane);
+    }
+    __syncthreads();
+    for (int b = nblk - 1; b >= 0; --b) {
+        const int b0 = b * kBlk;
+        if (b > 0) stage_load(rg, co, c, b0 - kBlk, 0, cut, lane);
+        const Stage& S = stg[buf];
+        const int top = min(kBlk, cut - b0) - 1;
+        if (mode == 0) {
+#pragma unroll 8
+            for (int t = top; t >= 0; --t) {
+                const d4 q4 = S.co[t];
+                const double cn = S.c[t];
 #pragma unroll
                 for (int q = 0; q < kPPTF; ++q) {
-                    const double Dn = fma(qv[k].x * dx[q], u[q], fma(qv[k].y, D[q], cv[k]));
-                    u[q] = fma(u[q], qv[k].z, Dn);
-                    D[q] = Dn;
+                    const double u0 = fma(fma(q4.x, xv[q], q4.y), s1[q], fma(-q4.z, s2[q], cn));
+                    s2[q] = s1[q];
+                    s1[q] = u0;
+                }
+            }
+        } else {
+#pragma unroll 8
+            for (int t = top; t >= 0; --t) {
+                const d4 q4 = S.co[t];
+                const double cn = S.c[t];
+                const bool last = (b0 + t) == 0;
+#pragma unroll
+                for (int q = 0; q < kPPTF; ++q) {
+                    const double Dn = fma(q4.x * xv[q], s1[q], fma(q4.y, s2[q], cn));
+                    if (!last) s1[q] = fma(s1[q], q4.z, Dn);
+                    s2[q] = Dn;
                 }
             }
         }
-        for (; n >= 1; --n) {
-            const d4 qn = ld(co + n);
-            const double cn = c[n];
-#pragma unroll
-            for (int q = 0; q < kPPTF; ++q) {
-                const double Dn = fma(qn.x * dx[q], u[q], fma(qn.y, D[q], cn));
-                u[q] = fma(u[q], qn.z, Dn);
-                D[q] = Dn;
-            }
-        }
-        if (cut >= 1) {
-            const d4 qn = ld(co);
-            const double cn = c[0];
-#pragma unroll
-            for (int q = 0; q < kPPTF; ++q) D[q] = fma(qn.x * dx[q], u[q], fma(qn.y, D[q], cn));
-        }
-#pragma unroll
-        for (int q = 0; q < kPPTF; ++q) res[q] = D[q];
+        if (b > 0) stage_store(stg[buf ^ 1], rg, lane);
+        __syncthreads();
+        buf ^= 1;
     }
 #pragma unroll
     for (int q = 0; q < kPPTF; ++q) {
         const int idx = lane + 64 * q;
-        if (idx < np) d.p[p0 + idx] = res[q];
+        if (idx < np) d.p[p0 + idx] = mode == 0 ? s1[q] : s2[q];
     }
 }
 
@@ -161,6 +168,7 @@ cjt_status launch_rec_fwd(const EngineArgs& a)
 __global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ descs)
 {
     __shared__ double red[kChunk][64 + 1];
+    __shared__ Stage stg[2];
     const ExecDesc& d = descs[blockIdx.x];
     const int task = blockIdx.y;
     if (task >= d.ntasks) return;
@@ -190,46 +198,61 @@ __global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ des
             xv[q] = mode > 0 ? -2.0 * sh * sh : 2.0 * ch * ch;
         }
     }
-    cptr<d4> co = as_const(mode == 0 ? d.rec0 : (mode > 0 ? d.recp : d.recm));
+    // three-term: (A_n, B_n, C_n);  modified: (A_n, C_n / r_{n-1}, r_n)
+    const d4* __restrict__ co = mode == 0 ? d.rec0 : (mode > 0 ? d.recp : d.recm);
     const int dd = lane >> 2, qq = lane & 3;  // reduction: degree dd of the chunk, quarter qq of the 64 lanes
-    for (int n0 = 0; n0 < cut; n0 += kChunk) {
-        const int nend = min(kChunk, cut - n0);
-#pragma unroll 4
-        for (int t = 0; t < nend; ++t) {
-            const int n = n0 + t;
-            double v = 0.0;
+    const int nblk = (cut + kBlk - 1) / kBlk;
+    StageRegs rg;
+    int buf = 0;
+    if (nblk > 0) {
+        stage_load(rg, co, nullptr, 0, 0, cut, lane);
+        stage_store(stg[0], rg, lane);
+    }
+    __syncthreads();
+    for (int b = 0; b < nblk; ++b) {
+        const int b0 = b * kBlk;
+        if (b + 1 < nblk) stage_load(rg, co, nullptr, b0 + kBlk, 0, cut, lane);
+        const Stage& S = stg[buf];
+        const int bend = min(kBlk, cut - b0);
+        for (int c0 = 0; c0 < bend; c0 += kChunk) {
+            const int nend = min(kChunk, bend - c0);
+#pragma unroll 8
+            for (int t = 0; t < nend; ++t) {
+                double v = 0.0;
 #pragma unroll
-            for (int q = 0; q < kPPT; ++q) v += pv[q];
-            red[t][lane] = v;
-            const d4 cf = ld(co + n);
-            if (mode == 0) {
-                // rec0 holds (A_n, B_n, C_n) for the three-term recurrence
+                for (int q = 0; q < kPPT; ++q) v += pv[q];
+                red[t][lane] = v;
+                const d4 cf = S.co[c0 + t];
+                if (mode == 0) {
 #pragma unroll
-                for (int q = 0; q < kPPT; ++q) {
-                    const double p1 = fma(fma(cf.x, xv[q], cf.y), pv[q], -cf.z * ev[q]);
-                    ev[q] = pv[q];
-                    pv[q] = p1;
-                }
-            } else {
-                // (A_n, C_n / r_{n-1}, r_n)
+                    for (int q = 0; q < kPPT; ++q) {
+                        const double p1 = fma(fma(cf.x, xv[q], cf.y), pv[q], -cf.z * ev[q]);
+                        ev[q] = pv[q];
+                        pv[q] = p1;
+                    }
+                } else {
 #pragma unroll
-                for (int q = 0; q < kPPT; ++q) {
-                    const double e1 = fma(cf.x * xv[q], pv[q], cf.y * ev[q]);
-                    pv[q] = fma(pv[q], cf.z, e1);
-                    ev[q] = e1;
+                    for (int q = 0; q < kPPT; ++q) {
+                        const double e1 = fma(cf.x * xv[q], pv[q], cf.y * ev[q]);
+                        pv[q] = fma(pv[q], cf.z, e1);
+                        ev[q] = e1;
+                    }
                 }
             }
-        }
-        __syncthreads();
-        if (dd < nend) {
-            double s = 0.0;
+            __syncthreads();
+            if (dd < nend) {
+                double sum = 0.0;
 #pragma unroll
-            for (int l = 0; l < 16; ++l) s += red[dd][qq * 16 + l];
-            s += __shfl_xor(s, 1);
-            s += __shfl_xor(s, 2);
-            if (qq == 0) part[n0 + dd] = s;
+                for (int l = 0; l < 16; ++l) sum += red[dd][qq * 16 + l];
+                sum += __shfl_xor(sum, 1);
+                sum += __shfl_xor(sum, 2);
+                if (qq == 0) part[b0 + c0 + dd] = sum;
+            }
+            __syncthreads();
         }
+        if (b + 1 < nblk) stage_store(stg[buf ^ 1], rg, lane);
         __syncthreads();
+        buf ^= 1;
     }
 }
 
