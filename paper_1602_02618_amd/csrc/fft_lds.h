@@ -205,3 +205,86 @@ __device__ __forceinline__ void lds_fft(cx<T>* buf, int logF, int nfft, const cx
 }
 
 }  // namespace cjt
+
+namespace cjt {
+
+// ---------------------------------------------------------------------------
+// Register-resident variant for F >= 16: the caller loads the first stage's
+// inputs straight into registers and takes the last stage's outputs from
+// registers, so only the exchanges between stages go through LDS.
+//
+// Thread `lt` (of F/16 per transform) holds on entry v[r] = x[lt + r F/16],
+// r = 0..15.  On exit v[s] holds X[fft_out_index(s, lt, logF)].
+// buf is this transform's LDS slice (F elements, padded indices).
+
+__device__ __forceinline__ int fft_last_log_radix(int logF)
+{
+    const int rem = logF & 3;
+    return rem == 0 ? 4 : rem;
+}
+
+// Output position of register slot s (0..15) after fft_reg.
+__device__ __forceinline__ int fft_out_index(int s, int lt, int logF)
+{
+    const int F = 1 << logF;
+    const int lr = fft_last_log_radix(logF);
+    const int R = 1 << lr;
+    const int q = s >> lr, r = s & (R - 1);  // butterfly q of the thread, output r
+    return lt + q * (F >> 4) + r * (F >> lr);
+}
+
+template <typename T, int R, int BPT>
+__device__ __forceinline__ void fft_reg_last(cx<T> (&v)[16], const cx<T>* buf, int F, int Ns, int lt,
+                                             const cx<T>* __restrict__ tw, int64_t twmul)
+{
+    const int FR = F / R;
+    const int stride = FR / BPT;
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+        const int j = lt + q * stride;
+        const int k = j & (Ns - 1);
+        cx<T> w[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) w[r] = buf[lds_pad(j + r * FR)];
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[r] = cmul(w[r], tw[(int64_t)(r * k) * twmul]);
+        dft<T, R>(w);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q * R + r] = w[r];
+    }
+}
+
+// All threads of the workgroup must call this (it contains barriers); `active`
+// marks threads that own a transform.
+template <typename T>
+__device__ __forceinline__ void fft_reg(cx<T> (&v)[16], cx<T>* buf, int logF, int lt, bool active,
+                                        const cx<T>* __restrict__ tw, int64_t L2x)
+{
+    const int F = 1 << logF;
+    const int nst = (logF + 3) >> 2;  // stages: radix 16 ..., last one radix 2^(logF - 4(nst-1))
+    if (active) dft16(v);
+    if (nst == 1) return;
+    // first stage output (Ns = 1): positions 16 lt + r
+    if (active) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) buf[lds_pad(16 * lt + r)] = v[r];
+    }
+    __syncthreads();
+    int Ns = 16;
+    for (int st = 1; st + 1 < nst; ++st) {
+        // middle radix-16 stages through LDS
+        fft_stage<T, 16, 1>(buf, F, Ns, lt, 0, active, tw, L2x / ((int64_t)Ns << 4));
+        Ns <<= 4;
+    }
+    const int lr = logF - 4 * (nst - 1);
+    const int64_t twmul = L2x / ((int64_t)Ns << lr);
+    if (active) {
+        if (lr == 4) fft_reg_last<T, 16, 1>(v, buf, F, Ns, lt, tw, twmul);
+        else if (lr == 3) fft_reg_last<T, 8, 2>(v, buf, F, Ns, lt, tw, twmul);
+        else if (lr == 2) fft_reg_last<T, 4, 4>(v, buf, F, Ns, lt, tw, twmul);
+        else fft_reg_last<T, 2, 8>(v, buf, F, Ns, lt, tw, twmul);
+    }
+    __syncthreads();
+}
+
+}  // namespace cjt

@@ -27,6 +27,8 @@
 // both Z_s and Z_{L-s} for the untangling.  The row pass loops over all Hahn
 // terms (m) and blocks (k) of its rows and accumulates in registers, so each
 // output is written once.
+#include <algorithm>
+
 #include "cjt_internal.h"
 #include "fft_lds.h"
 
@@ -117,8 +119,8 @@ struct Source<Src::Moments> {
 };
 
 // ------------------------------------------------------------------ sinks
-// accumulate() sees every output index s in [0, L] exactly once per job;
-// slot identifies a register accumulator private to the calling thread.
+// contrib() sees every output index s in [0, L] exactly once per job and
+// returns what that job adds to output s; finish() stores the sum over jobs.
 
 constexpr int kSlots = 20;
 constexpr int kEPT = 8;  // row-pass elements per thread: 2048 per 256-thread workgroup
@@ -128,12 +130,12 @@ struct Target;
 
 template <>
 struct Target<Sink::FwdAsy> {
-    __device__ static void accumulate(const ExecDesc& d, int job, int64_t i, cx<double> X, double* acc, int slot)
+    __device__ static double contrib(const ExecDesc& d, int job, int64_t i, cx<double> X)
     {
         const int k = job / d.M, m = job - k * d.M;
-        if (i < d.win_lo[k] || i > d.win_hi[k]) return;
+        if (i < d.win_lo[k] || i > d.win_hi[k]) return 0.0;
         const cx<double> uv = d.uv[(int64_t)m * (d.G + 1) + i];
-        acc[slot] = fma(uv.re, X.re, fma(uv.im, X.im, acc[slot]));
+        return fma(uv.re, X.re, uv.im * X.im);
     }
     // every point is written (zero outside the windows); the final DCT-I adds
     // the recurrence part
@@ -142,11 +144,11 @@ struct Target<Sink::FwdAsy> {
 
 template <>
 struct Target<Sink::InvAsy> {
-    __device__ static void accumulate(const ExecDesc& d, int job, int64_t n, cx<double> X, double* acc, int slot)
+    __device__ static double contrib(const ExecDesc& d, int job, int64_t n, cx<double> X)
     {
         const int k = job / d.M, m = job - k * d.M;
-        if (n < d.deg_lo[k] || n >= d.deg_hi[k]) return;
-        acc[slot] = fma(d.C[(int64_t)m * (d.N + 1) + n], X.re + X.im, acc[slot]);
+        if (n < d.deg_lo[k] || n >= d.deg_hi[k]) return 0.0;
+        return d.C[(int64_t)m * (d.N + 1) + n] * (X.re + X.im);
     }
     // Every degree 0..N is written (zero outside the blocks); the recurrence
     // reduction adds its part and applies 1/A_n afterwards.
@@ -158,10 +160,7 @@ struct Target<Sink::InvAsy> {
 
 template <>
 struct Target<Sink::FwdFinal> {
-    __device__ static void accumulate(const ExecDesc&, int, int64_t, cx<double> X, double* acc, int slot)
-    {
-        acc[slot] = X.re;
-    }
+    __device__ static double contrib(const ExecDesc&, int, int64_t, cx<double> X) { return X.re; }
     __device__ static void finish(const ExecDesc& d, int64_t k, double v)
     {
         const int64_t N = d.N;
@@ -172,19 +171,13 @@ struct Target<Sink::FwdFinal> {
 
 template <>
 struct Target<Sink::InvInit> {
-    __device__ static void accumulate(const ExecDesc&, int, int64_t, cx<double> X, double* acc, int slot)
-    {
-        acc[slot] = X.re;
-    }
+    __device__ static double contrib(const ExecDesc&, int, int64_t, cx<double> X) { return X.re; }
     __device__ static void finish(const ExecDesc& d, int64_t j, double v) { d.p[j] = d.w[j] * v; }
 };
 
 template <>
 struct Target<Sink::Weights> {
-    __device__ static void accumulate(const ExecDesc&, int, int64_t, cx<double> X, double* acc, int slot)
-    {
-        acc[slot] = X.re;
-    }
+    __device__ static double contrib(const ExecDesc&, int, int64_t, cx<double> X) { return X.re; }
     // w_j = (1 - (d_j0 + d_jG)/2) / (G/2) Re X_j
     __device__ static void finish(const ExecDesc& d, int64_t j, double v)
     {
@@ -222,7 +215,8 @@ __device__ __forceinline__ cx<T> to_t(cx<double> v) { return {(T)v.re, (T)v.im};
 // One workgroup per instance; the whole length-L transform lives in LDS.
 // Loops over all jobs of the instance and accumulates per thread.
 template <typename T, Src S, Sink K>
-__global__ void __launch_bounds__(256) k_single(const ExecDesc* __restrict__ descs, FftGeom g, int max_jobs)
+__global__ void __launch_bounds__(256) k_single(const ExecDesc* __restrict__ descs, FftGeom g, int max_jobs,
+                                                size_t acc_off)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -231,16 +225,16 @@ __global__ void __launch_bounds__(256) k_single(const ExecDesc* __restrict__ des
     const int tid = threadIdx.x, nth = blockDim.x;
     const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
     const int nel = L / 2 + 1;  // elements s = 0..L/2
-    double acc[kSlots];
-#pragma unroll
-    for (int i = 0; i < kSlots; ++i) acc[i] = 0.0;
+    // per-thread accumulators in LDS: acc[slot * nth + tid]
+    double* acc = reinterpret_cast<double*>(smem_raw + acc_off);
+    for (int i = 0; i < kSlots; ++i) acc[i * nth + tid] = 0.0;
 
     for (int job = 0; job < max_jobs; ++job) {
         if (!Source<S>::valid(d, job)) break;
         for (int t = tid; t < L; t += nth) buf[lds_pad(t)] = to_t<T>(Source<S>::load(d, job, t));
         __syncthreads();
         lds_fft<T>(buf, g.logL, 1, tw, 2 * g.L);
-#pragma unroll
+#pragma unroll 2
         for (int q = 0; q < kSlots / 2; ++q) {
             const int s = tid + q * nth;
             if (s >= nel) break;
@@ -256,8 +250,8 @@ __global__ void __launch_bounds__(256) k_single(const ExecDesc* __restrict__ des
             } else {
                 untangle<T>(buf[lds_pad(s)], buf[lds_pad(L - s)], tw[s], xa, xb);
             }
-            Target<K>::accumulate(d, job, s, xa, acc, 2 * q);
-            if (2 * s != L) Target<K>::accumulate(d, job, L - s, xb, acc, 2 * q + 1);
+            acc[(2 * q) * nth + tid] += Target<K>::contrib(d, job, s, xa);
+            if (2 * s != L) acc[(2 * q + 1) * nth + tid] += Target<K>::contrib(d, job, L - s, xb);
         }
         __syncthreads();
     }
@@ -265,51 +259,52 @@ __global__ void __launch_bounds__(256) k_single(const ExecDesc* __restrict__ des
     for (int q = 0; q < kSlots / 2; ++q) {
         const int s = tid + q * nth;
         if (s >= nel) break;
-        Target<K>::finish(d, s, acc[2 * q]);
-        if (2 * s != L) Target<K>::finish(d, L - s, acc[2 * q + 1]);
+        Target<K>::finish(d, s, acc[(2 * q) * nth + tid]);
+        if (2 * s != L) Target<K>::finish(d, L - s, acc[(2 * q + 1) * nth + tid]);
     }
 }
 
 // ------------------------------------------------------------------ two passes
 
-// Column pass: TC consecutive columns n2 per workgroup, L1-point FFTs over n1,
-// multiply by exp(2 pi i n2 k1 / L), write tmp[job][k1 * L2 + n2].
+// Column pass: TC consecutive columns n2 per workgroup, L1-point FFTs over n1
+// held in registers (thread lt of a column owns n1 = lt + r L1/16), multiplied
+// by exp(2 pi i n2 k1 / L) and written to tmp[job][k1 L2 + n2].
 template <typename T, Src S>
 __global__ void __launch_bounds__(256) k_pass1(const ExecDesc* __restrict__ descs, FftGeom g, int TC)
 {
     extern __shared__ unsigned char smem_raw[];
-    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     const ExecDesc& d = descs[blockIdx.z];
     const int job = blockIdx.y;
     if (!Source<S>::valid(d, job)) return;
     const int L1 = g.L1, L2 = g.L2;
     const int64_t L = g.L;
-    const int col0 = blockIdx.x * TC;
-    const int tid = threadIdx.x, nth = blockDim.x;
+    const int tid = threadIdx.x;
+    const int c = tid % TC, lt = tid / TC;
+    const int64_t col = (int64_t)blockIdx.x * TC + c;
     const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
-    const int total = TC * L1;
-    for (int e = tid; e < total; e += nth) {
-        const int c = e % TC, n1 = e / TC;
-        const int64_t t = (int64_t)n1 * L2 + col0 + c;
-        buf[lds_pad(c * L1 + n1)] = to_t<T>(Source<S>::load(d, job, t));
-    }
-    __syncthreads();
-    lds_fft<T>(buf, g.logL1, TC, tw, 2 * L);
+    const int step = L1 >> 4;
+    cx<T> v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = to_t<T>(Source<S>::load(d, job, (int64_t)(lt + r * step) * L2 + col));
+    fft_reg<T>(v, lds + lds_pad(c * L1), g.logL1, lt, true, tw, 2 * L);
     cx<T>* out = reinterpret_cast<cx<T>*>(d.tmp) + (int64_t)job * L;
-    for (int e = tid; e < total; e += nth) {
-        const int c = e % TC, k1 = e / TC;
-        const int64_t n2 = col0 + c;
-        const int64_t q = (2 * n2 * k1) & (2 * L - 1);  // exp(2 pi i n2 k1 / L) = tw[2 n2 k1 mod 2L]
-        out[(int64_t)k1 * L2 + n2] = cmul(buf[lds_pad(c * L1 + k1)], tw[q]);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int64_t k1 = fft_out_index(s, lt, g.logL1);
+        const int64_t q = (2 * col * k1) & (2 * L - 1);  // exp(2 pi i n2 k1 / L) = tw[2 n2 k1 mod 2L]
+        out[k1 * L2 + col] = cmul(v[s], tw[q]);
     }
 }
 
 // Row pass: TU units per workgroup; unit u holds rows u and L1-u (unit 0 holds
 // rows 0 and L1/2).  Element (u, k2) pairs Z at row u, position k2 with Z at
 // row L1-u, position L2-1-k2, which are Z_s and Z_{L-s} for s = u + L1 k2.
+// The L2-point FFTs run in registers; their outputs go through LDS once so
+// that each thread can fetch both members of its pairs.
 template <typename T, Sink K>
 __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ descs, FftGeom g, int TU, int max_jobs,
-                                               int src_single_job)
+                                               int src_single_job, size_t acc_off)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -319,29 +314,31 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
     const int unit0 = blockIdx.x * TU;
     const int tid = threadIdx.x, nth = blockDim.x;
     const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
-    // TU * L2 = 2048 regular elements per workgroup, kEPT = 8 per thread
+    const int tpr = L2 >> 4;               // threads per row
+    const int rs = tid / tpr, lt = tid - rs * tpr;
+    const int my_unit = unit0 + (rs >> 1);
+    const int my_row = (rs & 1) == 0 ? my_unit : (my_unit == 0 ? L1 / 2 : L1 - my_unit);
+    // TU * L2 regular elements per workgroup, kEPT = 8 per thread (nth = TU L2 / 8)
     constexpr int ept = kEPT;
     const bool has_half = (unit0 == 0) && (tid == nth - 1);  // thread that also owns s = L/2
 
-    double acc[kSlots];
-#pragma unroll
-    for (int i = 0; i < kSlots; ++i) acc[i] = 0.0;
+    // per-thread accumulators in LDS: acc[slot * nth + tid], slots 0..2*ept (2*ept = s = L/2)
+    double* acc = reinterpret_cast<double*>(smem_raw + acc_off);
+    for (int i = 0; i <= 2 * ept; ++i) acc[i * nth + tid] = 0.0;
 
     const int njobs = src_single_job ? 1 : max_jobs;
     for (int job = 0; job < njobs; ++job) {
         if (!src_single_job && job >= d.nblk * d.M) break;
-        const cx<T>* in = reinterpret_cast<const cx<T>*>(d.tmp) + (int64_t)job * L;
-        // load 2*TU rows of L2
-        for (int e = tid; e < 2 * TU * L2; e += nth) {
-            const int r = e / L2, pos = e - r * L2;
-            const int lu = r >> 1;
-            const int unit = unit0 + lu;
-            const int row = (r & 1) == 0 ? unit : (unit == 0 ? L1 / 2 : L1 - unit);
-            buf[lds_pad(r * L2 + pos)] = in[(int64_t)row * L2 + pos];
-        }
-        __syncthreads();
-        lds_fft<T>(buf, g.logL2, 2 * TU, tw, 2 * L);
+        const cx<T>* in = reinterpret_cast<const cx<T>*>(d.tmp) + (int64_t)job * L + (int64_t)my_row * L2;
+        cx<T> v[16];
 #pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = in[lt + r * tpr];
+        cx<T>* slice = buf + lds_pad(rs * L2);
+        fft_reg<T>(v, slice, g.logL2, lt, true, tw, 2 * L);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) slice[lds_pad(fft_out_index(s, lt, g.logL2))] = v[s];
+        __syncthreads();
+#pragma unroll 2
         for (int q = 0; q < ept; ++q) {
             const int eps = tid + q * nth;
             const int lu = eps % TU, k2 = eps / TU;
@@ -367,12 +364,12 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
                 s = unit + (int64_t)L1 * k2;
                 untangle<T>(buf[lds_pad(ra * L2 + k2)], buf[lds_pad(rb * L2 + L2 - 1 - k2)], tw[s], xa, xb);
             }
-            Target<K>::accumulate(d, job, s, xa, acc, 2 * q);
-            Target<K>::accumulate(d, job, L - s, xb, acc, 2 * q + 1);
+            acc[(2 * q) * nth + tid] += Target<K>::contrib(d, job, s, xa);
+            acc[(2 * q + 1) * nth + tid] += Target<K>::contrib(d, job, L - s, xb);
         }
         if (has_half) {
             cx<T> z = buf[lds_pad(0 * L2 + L2 / 2)];  // row 0, position L2/2: s = L/2
-            Target<K>::accumulate(d, job, L / 2, cx<double>{(double)z.re, (double)z.im}, acc, kSlots - 1);
+            acc[(2 * ept) * nth + tid] += Target<K>::contrib(d, job, L / 2, cx<double>{(double)z.re, (double)z.im});
         }
         __syncthreads();
     }
@@ -389,10 +386,10 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
         } else {
             s = unit + (int64_t)L1 * k2;
         }
-        Target<K>::finish(d, s, acc[2 * q]);
-        Target<K>::finish(d, L - s, acc[2 * q + 1]);
+        Target<K>::finish(d, s, acc[(2 * q) * nth + tid]);
+        Target<K>::finish(d, L - s, acc[(2 * q + 1) * nth + tid]);
     }
-    if (has_half) Target<K>::finish(d, L / 2, acc[kSlots - 1]);
+    if (has_half) Target<K>::finish(d, L / 2, acc[(2 * ept) * nth + tid]);
 }
 
 // ------------------------------------------------------------------ launch
@@ -425,29 +422,35 @@ cjt_status run(const EngineArgs& a)
         if (nth < 64) nth = 64;
         if (nth > 256) nth = 256;
         if ((L / 2 + 1 + nth - 1) / nth > kSlots / 2) return fail(CJT_EUNSUPPORTED, "single-pass length too large");
-        cjt_status st = allow_lds(k_single<T, S, K>, lds_bytes(L, esz));
+        const size_t acc_off = (lds_bytes(L, esz) + 255) & ~(size_t)255;
+        const size_t total = acc_off + sizeof(double) * kSlots * nth;
+        cjt_status st = allow_lds(k_single<T, S, K>, total);
         if (st != CJT_OK) return st;
-        hipLaunchKernelGGL((k_single<T, S, K>), dim3(a.count), dim3(nth), lds_bytes(L, esz), a.stream, a.d_desc, g,
-                           max_jobs);
+        hipLaunchKernelGGL((k_single<T, S, K>), dim3(a.count), dim3(nth), total, a.stream, a.d_desc, g, max_jobs,
+                           acc_off);
         CJT_HIP_TRY(hipGetLastError());
         return CJT_OK;
     }
-    // two passes; all workgroups use 256 threads (16 values per thread per stage)
-    const int per_wg = 256 * 16;                 // complex values held per workgroup
-    const int TC = per_wg / g.L1;                // columns per pass-1 workgroup
-    const int TU = per_wg / (2 * g.L2);          // row pairs per pass-2 workgroup
-    if (TC < 1 || TU < 1 || g.L2 % TC != 0 || (g.L1 / 2) % TU != 0)
+    // two passes: 2048 complex values per workgroup in the column pass (TC
+    // columns of L1) and TU row pairs of L2 (at least 2048 values) in the row pass;
+    // every thread holds 16 values of one transform.
+    const int TC = std::max(1, 2048 / g.L1);
+    const int TU = std::max(1, 1024 / g.L2);
+    const int nth1 = TC * (g.L1 / 16), nth2 = 2 * TU * (g.L2 / 16);
+    if (g.L2 % TC != 0 || (g.L1 / 2) % TU != 0 || nth1 > 256 || nth2 > 256 || TU * g.L2 != nth2 * kEPT)
         return fail(CJT_EUNSUPPORTED, "FFT split not supported");
-    if (TU * g.L2 != 256 * kEPT) return fail(CJT_EUNSUPPORTED, "row pass geometry");
-    cjt_status st = allow_lds(k_pass1<T, S>, lds_bytes(per_wg, esz));
-    if (st == CJT_OK) st = allow_lds(k_pass2<T, K>, lds_bytes(per_wg, esz));
+    const size_t lds1 = lds_bytes(TC * g.L1, esz);
+    const size_t acc_off = (lds_bytes(2 * TU * g.L2, esz) + 255) & ~(size_t)255;
+    const size_t lds2 = acc_off + sizeof(double) * (2 * kEPT + 1) * nth2;
+    cjt_status st = allow_lds(k_pass1<T, S>, lds1);
+    if (st == CJT_OK) st = allow_lds(k_pass2<T, K>, lds2);
     if (st != CJT_OK) return st;
     dim3 g1(g.L2 / TC, max_jobs, a.count);
-    hipLaunchKernelGGL((k_pass1<T, S>), g1, dim3(256), lds_bytes(per_wg, esz), a.stream, a.d_desc, g, TC);
+    hipLaunchKernelGGL((k_pass1<T, S>), g1, dim3(nth1), lds1, a.stream, a.d_desc, g, TC);
     CJT_HIP_TRY(hipGetLastError());
     dim3 g2((g.L1 / 2) / TU, 1, a.count);
-    hipLaunchKernelGGL((k_pass2<T, K>), g2, dim3(256), lds_bytes(per_wg, esz), a.stream, a.d_desc, g, TU, max_jobs,
-                       single_job ? 1 : 0);
+    hipLaunchKernelGGL((k_pass2<T, K>), g2, dim3(nth2), lds2, a.stream, a.d_desc, g, TU, max_jobs,
+                       single_job ? 1 : 0, acc_off);
     CJT_HIP_TRY(hipGetLastError());
     return CJT_OK;
 }
