@@ -62,33 +62,34 @@ hipEvent_t ev_get()
     return e;
 }
 
-// Brackets one launch with events on `st` when timing is enabled.
-struct ProfScope {
-    bool on = false;
-    ProfRec r{};
-    hipStream_t st = nullptr;
-    ProfScope(const char* name, double flops, double bytes, hipStream_t s)
-    {
-        std::lock_guard<std::mutex> lk(g_prof_mu);
-        if (!g_prof_on) return;
-        r.name = name;
-        r.flops = flops;
-        r.bytes = bytes;
-        r.a = ev_get();
-        r.b = ev_get();
-        st = s;
-        if (!r.a || !r.b) return;
-        on = hipEventRecord(r.a, st) == hipSuccess;
-    }
-    ~ProfScope()
-    {
-        if (!on) return;
-        std::lock_guard<std::mutex> lk(g_prof_mu);
-        if (hipEventRecord(r.b, st) == hipSuccess) g_prof.push_back(r);
-    }
-};
-
 }  // namespace
+
+ProfScope::ProfScope(const char* name, double flops, double bytes, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on || !name) return;
+    ProfRec r{};
+    r.name = name;
+    r.flops = flops;
+    r.bytes = bytes;
+    r.a = ev_get();
+    r.b = ev_get();
+    if (!r.a || !r.b) return;
+    if (hipEventRecord(r.a, s) != hipSuccess) return;
+    st = s;
+    slot = (int)g_prof.size();
+    g_prof.push_back(r);
+    on = true;
+}
+
+ProfScope::~ProfScope()
+{
+    if (!on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (slot >= 0 && slot < (int)g_prof.size()) {
+        if (hipEventRecord(g_prof[slot].b, st) != hipSuccess) g_prof[slot].name = nullptr;
+    }
+}
 
 // ------------------------------------------------------------------ workspace (one per stream)
 
@@ -192,6 +193,19 @@ Need need_of(const Plan& P, bool inverse, bool fp32)
 }
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Timing labels of an engine launch; the work is split between the column and
+// row passes in proportion to their FFT stages (half each) for two-pass
+// lengths, and all to the single pass otherwise.
+void label(EngineArgs& ea, const char* n1, const char* n2, double flops, double bytes)
+{
+    ea.name1 = n1;
+    ea.name2 = n2;
+    ea.flops1 = 0.5 * flops;
+    ea.flops2 = 0.5 * flops;
+    ea.bytes1 = 0.5 * bytes;
+    ea.bytes2 = 0.5 * bytes;
+}
 
 // Algorithmic work of one transform's kernels (see cjt_profile_enable).
 struct Work {
@@ -340,6 +354,7 @@ cjt_status execute(bool inverse, const std::vector<Inst>& insts, hipStream_t st)
             const Plan& P = *insts[order[c.first + q]].P;
             const Part& pt = inverse ? P.inv : P.fwd;
             ea.max_jobs = std::max(ea.max_jobs, pt.nblk * pt.M);
+            if (pt.nblk > 0) ea.max_m = std::max(ea.max_m, pt.M);
             Work x = work_of(P, inverse);
             wk->asy_flops += x.asy_flops;
             wk->bnd_flops += x.bnd_flops;
@@ -364,7 +379,8 @@ cjt_status execute(bool inverse, const std::vector<Inst>& insts, hipStream_t st)
             const int64_t N = insts[order[c.first]].P->N;
             if (ea.max_jobs > 0) {
                 if ((s = fft_geometry(N, fp32, st, &ea.geom)) != CJT_OK) return s;
-                ProfScope ps(fp32 ? "hahn_blocks_forward_fp32" : "hahn_blocks_forward", wk.asy_flops, wk.asy_bytes, st);
+                label(ea, fp32 ? "hahn_fwd_cols_fp32" : "hahn_fwd_cols", fp32 ? "hahn_fwd_rows_fp32" : "hahn_fwd_rows",
+                      wk.asy_flops, wk.asy_bytes);
                 if ((s = launch_rdft(ea, Src::FwdAsy, Sink::FwdAsy, fp32)) != CJT_OK) return s;
             }
         }
@@ -374,7 +390,7 @@ cjt_status execute(bool inverse, const std::vector<Inst>& insts, hipStream_t st)
             EngineArgs ea = chunk_args(c, &wk);
             const int64_t N = insts[order[c.first]].P->N;
             if ((s = fft_geometry(N, false, st, &ea.geom)) != CJT_OK) return s;
-            ProfScope ps("dct1_final_forward", wk.bnd_flops, wk.bnd_bytes, st);
+            label(ea, "dct1_final_cols", "dct1_final_rows", wk.bnd_flops, wk.bnd_bytes);
             if ((s = launch_rdft(ea, Src::FwdFinal, Sink::FwdFinal, false)) != CJT_OK) return s;
         }
     } else {
@@ -383,7 +399,7 @@ cjt_status execute(bool inverse, const std::vector<Inst>& insts, hipStream_t st)
             EngineArgs ea = chunk_args(c, &wk);
             const int64_t N = insts[order[c.first]].P->N;
             if ((s = fft_geometry(2 * N, false, st, &ea.geom)) != CJT_OK) return s;
-            ProfScope ps("dct1_initial_inverse", wk.bnd_flops, wk.bnd_bytes, st);
+            label(ea, "dct1_initial_cols", "dct1_initial_rows", wk.bnd_flops, wk.bnd_bytes);
             if ((s = launch_rdft(ea, Src::InvInit, Sink::InvInit, false)) != CJT_OK) return s;
         }
         CJT_HIP_TRY(hipEventRecord(ws.fork, st));
@@ -399,7 +415,8 @@ cjt_status execute(bool inverse, const std::vector<Inst>& insts, hipStream_t st)
             const int64_t N = insts[order[c.first]].P->N;
             if (ea.max_jobs > 0) {
                 if ((s = fft_geometry(2 * N, fp32, st, &ea.geom)) != CJT_OK) return s;
-                ProfScope ps(fp32 ? "hahn_blocks_inverse_fp32" : "hahn_blocks_inverse", wk.asy_flops, wk.asy_bytes, st);
+                label(ea, fp32 ? "hahn_inv_cols_fp32" : "hahn_inv_cols", fp32 ? "hahn_inv_rows_fp32" : "hahn_inv_rows",
+                      wk.asy_flops, wk.asy_bytes);
                 if ((s = launch_rdft(ea, Src::InvAsy, Sink::InvAsy, fp32)) != CJT_OK) return s;
             } else {
                 dim3 grid((unsigned)((N + 1 + 255) / 256), (unsigned)c.count);
@@ -516,6 +533,9 @@ cjt_status cjt_profile_collect(cjt_kernel_stat* out, int max, int* n_out)
     std::vector<cjt_kernel_stat> agg;
     cjt_status st = CJT_OK;
     for (ProfRec& r : g_prof) {
+        g_ev_pool.push_back(r.a);
+        g_ev_pool.push_back(r.b);
+        if (!r.name) continue;
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) st = fail(CJT_EDEVICE, "event timing failed");
         size_t i = 0;
@@ -530,8 +550,6 @@ cjt_status cjt_profile_collect(cjt_kernel_stat* out, int max, int* n_out)
         agg[i].total_ms += ms;
         agg[i].flops += r.flops;
         agg[i].bytes += r.bytes;
-        g_ev_pool.push_back(r.a);
-        g_ev_pool.push_back(r.b);
     }
     g_prof.clear();
     int n = (int)std::min<size_t>(agg.size(), (size_t)std::max(max, 0));

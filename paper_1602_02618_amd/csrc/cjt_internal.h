@@ -106,14 +106,31 @@ cjt_status fail(cjt_status st, const std::string& msg);
             return ::cjt::fail(CJT_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// Kernel timing (see cjt_profile_enable): brackets one launch with HIP events
+// on `stream` when timing is on, tagged with the launch's algorithmic work.
+struct ProfScope {
+    ProfScope(const char* name, double flops, double bytes, hipStream_t stream);
+    ~ProfScope();
+    ProfScope(const ProfScope&) = delete;
+    ProfScope& operator=(const ProfScope&) = delete;
+    bool on = false;
+    int slot = -1;
+    hipStream_t st = nullptr;
+};
+
 // Launchers implemented in the .hip files.
 struct EngineArgs {
     const ExecDesc* d_desc;   // device array of descriptors
     int count;                // instances in the launch
     int max_jobs;             // max nblk*M over the instances
+    int max_m;                // max M over the instances with blocks
     int max_tasks;            // max ntasks over the instances
     FftGeom geom;             // all instances of one launch share L
     hipStream_t stream;
+    // timing labels and algorithmic work of the engine's launches (column pass, row pass)
+    const char* name1 = nullptr;
+    const char* name2 = nullptr;
+    double flops1 = 0, flops2 = 0, bytes1 = 0, bytes2 = 0;
 };
 
 enum class Src { FwdAsy, InvAsy, FwdFinal, InvInit, Moments };

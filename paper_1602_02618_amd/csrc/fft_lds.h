@@ -21,6 +21,11 @@ namespace cjt {
 
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
 
+// Distance between the LDS slices of consecutive transforms of length F: the
+// padded length plus one element, so that threads of one wave working on
+// different slices do not land on the same bank.
+__host__ __device__ __forceinline__ int slice_stride(int F) { return F + (F >> 4) + 1; }
+
 template <typename T>
 __device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <typename T>

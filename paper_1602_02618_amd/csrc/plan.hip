@@ -456,6 +456,7 @@ cjt_status build_plan_device(Plan* P, hipStream_t st)
         ea.d_desc = dd;
         ea.count = 1;
         ea.max_jobs = 1;
+        ea.max_m = 1;
         stt = fft_geometry(2 * N, false, st, &ea.geom);
         if (stt != CJT_OK) break;
         ea.stream = st;

@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(256) k_pass1(const ExecDesc* __restrict__ desc
     cx<T> v[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = to_t<T>(Source<S>::load(d, job, (int64_t)(lt + r * step) * L2 + col));
-    fft_reg<T>(v, lds + lds_pad(c * L1), g.logL1, lt, true, tw, 2 * L);
+    fft_reg<T>(v, lds + c * slice_stride(L1), g.logL1, lt, true, tw, 2 * L);
     cx<T>* out = reinterpret_cast<cx<T>*>(d.tmp) + (int64_t)job * L;
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
@@ -326,14 +326,16 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
     double* acc = reinterpret_cast<double*>(smem_raw + acc_off);
     for (int i = 0; i <= 2 * ept; ++i) acc[i * nth + tid] = 0.0;
 
-    const int njobs = src_single_job ? 1 : max_jobs;
-    for (int job = 0; job < njobs; ++job) {
-        if (!src_single_job && job >= d.nblk * d.M) break;
+    // jobs in the order (m, k), k fastest, so that the diagonals of term m are
+    // re-read from L2 for every block
+    const int njobs = src_single_job ? 1 : d.nblk * d.M;
+    for (int it = 0; it < njobs; ++it) {
+        const int job = src_single_job ? 0 : (it % d.nblk) * d.M + it / d.nblk;
         const cx<T>* in = reinterpret_cast<const cx<T>*>(d.tmp) + (int64_t)job * L + (int64_t)my_row * L2;
         cx<T> v[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = in[lt + r * tpr];
-        cx<T>* slice = buf + lds_pad(rs * L2);
+        cx<T>* slice = buf + rs * slice_stride(L2);
         fft_reg<T>(v, slice, g.logL2, lt, true, tw, 2 * L);
 #pragma unroll
         for (int s = 0; s < 16; ++s) slice[lds_pad(fft_out_index(s, lt, g.logL2))] = v[s];
@@ -349,26 +351,26 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
             if (unit == 0) {
                 if (k2 < L2 / 2) {
                     s = L1 / 2 + (int64_t)L1 * k2;
-                    untangle<T>(buf[lds_pad(rb * L2 + k2)], buf[lds_pad(rb * L2 + L2 - 1 - k2)], tw[s], xa, xb);
+                    untangle<T>(buf[rb * slice_stride(L2) + lds_pad(k2)], buf[rb * slice_stride(L2) + lds_pad(L2 - 1 - k2)], tw[s], xa, xb);
                 } else if (k2 == L2 / 2) {
                     s = 0;
-                    cx<T> z = buf[lds_pad(ra * L2)];
+                    cx<T> z = buf[ra * slice_stride(L2)];
                     xa = {(double)z.re + (double)z.im, 0.0};
                     xb = {(double)z.re - (double)z.im, 0.0};
                 } else {
                     const int kk = k2 - L2 / 2;
                     s = (int64_t)L1 * kk;
-                    untangle<T>(buf[lds_pad(ra * L2 + kk)], buf[lds_pad(ra * L2 + L2 - kk)], tw[s], xa, xb);
+                    untangle<T>(buf[ra * slice_stride(L2) + lds_pad(kk)], buf[ra * slice_stride(L2) + lds_pad(L2 - kk)], tw[s], xa, xb);
                 }
             } else {
                 s = unit + (int64_t)L1 * k2;
-                untangle<T>(buf[lds_pad(ra * L2 + k2)], buf[lds_pad(rb * L2 + L2 - 1 - k2)], tw[s], xa, xb);
+                untangle<T>(buf[ra * slice_stride(L2) + lds_pad(k2)], buf[rb * slice_stride(L2) + lds_pad(L2 - 1 - k2)], tw[s], xa, xb);
             }
             acc[(2 * q) * nth + tid] += Target<K>::contrib(d, job, s, xa);
             acc[(2 * q + 1) * nth + tid] += Target<K>::contrib(d, job, L - s, xb);
         }
         if (has_half) {
-            cx<T> z = buf[lds_pad(0 * L2 + L2 / 2)];  // row 0, position L2/2: s = L/2
+            cx<T> z = buf[lds_pad(L2 / 2)];  // row 0, position L2/2: s = L/2
             acc[(2 * ept) * nth + tid] += Target<K>::contrib(d, job, L / 2, cx<double>{(double)z.re, (double)z.im});
         }
         __syncthreads();
@@ -426,6 +428,7 @@ cjt_status run(const EngineArgs& a)
         const size_t total = acc_off + sizeof(double) * kSlots * nth;
         cjt_status st = allow_lds(k_single<T, S, K>, total);
         if (st != CJT_OK) return st;
+        ProfScope ps(a.name1, a.flops1 + a.flops2, a.bytes1 + a.bytes2, a.stream);
         hipLaunchKernelGGL((k_single<T, S, K>), dim3(a.count), dim3(nth), total, a.stream, a.d_desc, g, max_jobs,
                            acc_off);
         CJT_HIP_TRY(hipGetLastError());
@@ -439,19 +442,25 @@ cjt_status run(const EngineArgs& a)
     const int nth1 = TC * (g.L1 / 16), nth2 = 2 * TU * (g.L2 / 16);
     if (g.L2 % TC != 0 || (g.L1 / 2) % TU != 0 || nth1 > 256 || nth2 > 256 || TU * g.L2 != nth2 * kEPT)
         return fail(CJT_EUNSUPPORTED, "FFT split not supported");
-    const size_t lds1 = lds_bytes(TC * g.L1, esz);
-    const size_t acc_off = (lds_bytes(2 * TU * g.L2, esz) + 255) & ~(size_t)255;
+    const size_t lds1 = (size_t)TC * slice_stride(g.L1) * esz;
+    const size_t acc_off = ((size_t)2 * TU * slice_stride(g.L2) * esz + 255) & ~(size_t)255;
     const size_t lds2 = acc_off + sizeof(double) * (2 * kEPT + 1) * nth2;
     cjt_status st = allow_lds(k_pass1<T, S>, lds1);
     if (st == CJT_OK) st = allow_lds(k_pass2<T, K>, lds2);
     if (st != CJT_OK) return st;
     dim3 g1(g.L2 / TC, max_jobs, a.count);
-    hipLaunchKernelGGL((k_pass1<T, S>), g1, dim3(nth1), lds1, a.stream, a.d_desc, g, TC);
-    CJT_HIP_TRY(hipGetLastError());
+    {
+        ProfScope ps(a.name1, a.flops1, a.bytes1, a.stream);
+        hipLaunchKernelGGL((k_pass1<T, S>), g1, dim3(nth1), lds1, a.stream, a.d_desc, g, TC);
+        CJT_HIP_TRY(hipGetLastError());
+    }
     dim3 g2((g.L1 / 2) / TU, 1, a.count);
-    hipLaunchKernelGGL((k_pass2<T, K>), g2, dim3(nth2), lds2, a.stream, a.d_desc, g, TU, max_jobs,
-                       single_job ? 1 : 0, acc_off);
-    CJT_HIP_TRY(hipGetLastError());
+    {
+        ProfScope ps(a.name2, a.flops2, a.bytes2, a.stream);
+        hipLaunchKernelGGL((k_pass2<T, K>), g2, dim3(nth2), lds2, a.stream, a.d_desc, g, TU, max_jobs,
+                           single_job ? 1 : 0, acc_off);
+        CJT_HIP_TRY(hipGetLastError());
+    }
     return CJT_OK;
 }
 
