@@ -93,8 +93,9 @@ typedef struct {
     size_t device_bytes;     /* device memory held by the plan */
 } cjt_plan_info;
 
-/* Create a plan for degree N >= 1 (a power of two in this build; other N
- * return CJT_EUNSUPPORTED), parameters (alpha, beta) in (-1/2, 1/2]
+/* Create a plan for degree 1 <= N <= 2^21 (larger N return CJT_EUNSUPPORTED;
+ * lengths that are not powers of two run their FFTs as chirp-z convolutions),
+ * parameters (alpha, beta) in (-1/2, 1/2]
  * (Sec. 2.1: Hahn's remainder bound), and M Hahn terms (0 = chosen by the
  * library's cost model, else 2 <= M <= 30; Sec. 2.2 needs M >= 2).  flags is
  * CJT_FP64 or CJT_FP32_BULK.  Plan arrays are computed on the device on

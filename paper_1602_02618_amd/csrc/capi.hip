@@ -177,7 +177,6 @@ struct Need {
 
 Need need_of(const Plan& P, bool inverse, bool fp32)
 {
-    const size_t esz = fp32 ? 8 : 16;
     const Part& pt = inverse ? P.inv : P.fwd;
     const int64_t L = inverse ? 2 * P.N : P.N;
     Need n;
@@ -185,10 +184,9 @@ Need need_of(const Plan& P, bool inverse, bool fp32)
     n.p2 = inverse ? 0 : sizeof(double) * (size_t)(P.N + 1);
     n.part = inverse ? sizeof(double) * (size_t)std::max<int64_t>(1, P.part_total_i) : 0;
     const int64_t jobs = (int64_t)pt.nblk * pt.M;
-    const bool two_pass = L > kSingleMax;
-    n.tmp = two_pass ? esz * (size_t)std::max<int64_t>(jobs, 1) * (size_t)L : 0;
-    // boundary DCTs (FP64) also need an intermediate in the two-pass case
-    if (two_pass) n.tmp = std::max(n.tmp, (size_t)16 * (size_t)L);
+    n.tmp = (size_t)std::max<int64_t>(jobs, 1) * fft_job_bytes(L, fp32);
+    // the boundary DCTs (FP64) may need an intermediate as well
+    n.tmp = std::max(n.tmp, fft_job_bytes(L, false));
     return n;
 }
 
@@ -454,8 +452,7 @@ void fill_part_info(const Part& p, cjt_partition_info* o)
 cjt_status check_args(int64_t N, double alpha, double beta, int M, unsigned flags)
 {
     if (N < 1) return fail(CJT_EINVAL, "N must be >= 1");
-    if ((N & (N - 1)) != 0) return fail(CJT_EUNSUPPORTED, "N must be a power of two in this build");
-    if (N > ((int64_t)1 << 24)) return fail(CJT_EUNSUPPORTED, "N above 2^24 is not supported");
+    if (N > kMaxN) return fail(CJT_EUNSUPPORTED, "N above 2^21 is not supported");
     if (!isfinite(alpha) || !isfinite(beta) || !(alpha > -0.5 && alpha <= 0.5) || !(beta > -0.5 && beta <= 0.5))
         return fail(CJT_EDOMAIN, "alpha and beta must lie in (-1/2, 1/2]");
     if (M != 0 && (M < 2 || M > kMaxM)) return fail(CJT_EDOMAIN, "M must be 0 (auto) or in [2, 30]");

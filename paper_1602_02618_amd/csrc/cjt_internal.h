@@ -83,17 +83,32 @@ __device__ __forceinline__ d4 ld(cptr<d4> p) { return d4{p->x, p->y, p->z, p->w}
 // Wave-uniform copy of an int (the value must already be equal in all lanes).
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Geometry of one complex FFT length L (a power of two) on the device.
+// Geometry of one complex FFT length L on the device.  Powers of two run
+// directly; any other L runs as a cyclic convolution of power-of-two length
+// P >= 2L-1 (Bluestein's chirp-z identity), with the same radix kernels.
 struct FftGeom {
     int64_t L;        // complex length
     int32_t logL;
-    int32_t single;   // 1: whole transform in one workgroup (L <= kSingleMax)
-    int32_t L1, L2;   // two-pass split, L = L1 * L2 (column pass over L1, row pass over L2)
+    int32_t single;   // 1: whole transform in one workgroup
+    int32_t L1, L2;   // two-pass split of the power-of-two length (L, or P for chirp-z)
     int32_t logL1, logL2;
-    const void* tw;   // [2L] e^{i pi q / L}, in the precision of the transform
+    const void* tw;   // [2L'] e^{i pi q / L'}, L' = L (power of two) or P (chirp-z)
+    // chirp-z only
+    int32_t bluestein;
+    int32_t logP;
+    int64_t P;
+    const void* chirp;  // [L]   e^{i pi t^2 / L}
+    const void* bl;     // [P]   FFT_P of the kernel conj(chirp) wrapped cyclically
+    const void* utw;    // [L+1] e^{i pi s / L}, twiddles of the real-input untangling
 };
 
 constexpr int64_t kSingleMax = 4096;
+// Largest degree: the inverse's length-2N transform must fit the two-pass
+// engine (power-of-two lengths up to 2^22, chirp-z convolutions up to 2^24).
+constexpr int64_t kMaxN = (int64_t)1 << 21;
+
+// Bytes of intermediate storage one job of the FFT engine needs for length L.
+size_t fft_job_bytes(int64_t L, bool fp32);
 
 // Error reporting (thread-local detail message).
 void set_error(const std::string& msg);
@@ -141,5 +156,7 @@ cjt_status launch_rec_fwd(const EngineArgs& a);
 cjt_status launch_rec_inv(const EngineArgs& a);
 cjt_status launch_rec_inv_reduce(const EngineArgs& a, int64_t maxN);
 cjt_status make_twiddles(int64_t L, bool fp32, const void** out, hipStream_t stream);
+cjt_status fft_twiddles_cached(int64_t L, bool fp32, hipStream_t st, const void** out);
+cjt_status make_chirp_tables(FftGeom* g, bool fp32, hipStream_t st);
 
 }  // namespace cjt

@@ -462,8 +462,9 @@ cjt_status build_plan_device(Plan* P, hipStream_t st)
         ea.stream = st;
         // two-pass transforms need an intermediate buffer
         void* tmp = nullptr;
-        if (!ea.geom.single) {
-            if (hipMalloc(&tmp, sizeof(cx<double>) * (size_t)(2 * N)) != hipSuccess) {
+        const size_t tmp_bytes = fft_job_bytes(2 * N, false);
+        if (tmp_bytes > 0) {
+            if (hipMalloc(&tmp, tmp_bytes) != hipSuccess) {
                 stt = fail(CJT_ENOMEM, "weights workspace");
                 break;
             }
@@ -486,51 +487,89 @@ cjt_status build_plan_device(Plan* P, hipStream_t st)
 // ------------------------------------------------------------------ FFT geometry cache
 
 namespace {
-struct TwKey {
+struct GeoEntry {
     int dev;
     int64_t L;
     bool fp32;
-    bool operator<(const TwKey& o) const
-    {
-        if (dev != o.dev) return dev < o.dev;
-        if (L != o.L) return L < o.L;
-        return fp32 < o.fp32;
-    }
+    FftGeom g;
 };
-std::mutex g_tw_mu;
-std::vector<std::pair<TwKey, const void*>> g_tw;
-}  // namespace
+std::recursive_mutex g_geo_mu;
+std::vector<std::pair<GeoEntry, const void*>> g_tw;  // power-of-two twiddle tables
+std::vector<GeoEntry> g_geo;                          // complete geometries
 
-cjt_status fft_geometry(int64_t L, bool fp32, hipStream_t st, FftGeom* g)
+int ilog2_ceil(int64_t x)
 {
-    if (L < 1 || (L & (L - 1)) != 0) return fail(CJT_EUNSUPPORTED, "FFT length must be a power of two");
-    int dev = 0;
-    CJT_HIP_TRY(hipGetDevice(&dev));
-    const void* tw = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(g_tw_mu);
-        for (auto& e : g_tw)
-            if (e.first.dev == dev && e.first.L == L && e.first.fp32 == fp32) tw = e.second;
-        if (!tw) {
-            cjt_status s = make_twiddles(L, fp32, &tw, st);
-            if (s != CJT_OK) return s;
-            CJT_HIP_TRY(hipStreamSynchronize(st));
-            g_tw.push_back({TwKey{dev, L, fp32}, tw});
-        }
-    }
-    *g = FftGeom{};
-    g->L = L;
     int lg = 0;
-    while (((int64_t)1 << lg) < L) ++lg;
-    g->logL = lg;
-    g->tw = tw;
-    g->single = L <= kSingleMax ? 1 : 0;
+    while (((int64_t)1 << lg) < x) ++lg;
+    return lg;
+}
+
+void split(FftGeom* g, int lg, int64_t F)
+{
+    g->single = F <= kSingleMax ? 1 : 0;
     if (!g->single) {
         g->logL1 = lg / 2;
         g->logL2 = lg - g->logL1;
         g->L1 = 1 << g->logL1;
         g->L2 = 1 << g->logL2;
     }
+}
+}  // namespace
+
+// Twiddles e^{i pi q / F}, q < 2F, of a power-of-two length F, built once per
+// (device, F, precision) and kept for the life of the process.
+cjt_status fft_twiddles_cached(int64_t F, bool fp32, hipStream_t st, const void** out)
+{
+    int dev = 0;
+    CJT_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::recursive_mutex> lk(g_geo_mu);
+    for (auto& e : g_tw)
+        if (e.first.dev == dev && e.first.L == F && e.first.fp32 == fp32) {
+            *out = e.second;
+            return CJT_OK;
+        }
+    const void* tw = nullptr;
+    cjt_status s = make_twiddles(F, fp32, &tw, st);
+    if (s != CJT_OK) return s;
+    CJT_HIP_TRY(hipStreamSynchronize(st));
+    g_tw.push_back({GeoEntry{dev, F, fp32, FftGeom{}}, tw});
+    *out = tw;
+    return CJT_OK;
+}
+
+// Geometry of the length-L complex FFT: power-of-two lengths run directly
+// (one or two passes), every other length through the chirp-z convolution of
+// power-of-two length P >= 2L - 1.
+cjt_status fft_geometry(int64_t L, bool fp32, hipStream_t st, FftGeom* g)
+{
+    if (L < 1) return fail(CJT_EINVAL, "FFT length must be positive");
+    int dev = 0;
+    CJT_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::recursive_mutex> lk(g_geo_mu);
+    for (auto& e : g_geo)
+        if (e.dev == dev && e.L == L && e.fp32 == fp32) {
+            *g = e.g;
+            return CJT_OK;
+        }
+    FftGeom x{};
+    x.L = L;
+    x.logL = ilog2_ceil(L);
+    if ((L & (L - 1)) == 0) {
+        cjt_status s = fft_twiddles_cached(L, fp32, st, &x.tw);
+        if (s != CJT_OK) return s;
+        split(&x, x.logL, L);
+    } else {
+        x.bluestein = 1;
+        x.logP = ilog2_ceil(2 * L - 1);
+        x.P = (int64_t)1 << x.logP;
+        cjt_status s = fft_twiddles_cached(x.P, fp32, st, &x.tw);
+        if (s != CJT_OK) return s;
+        split(&x, x.logP, x.P);
+        s = make_chirp_tables(&x, fp32, st);
+        if (s != CJT_OK) return s;
+    }
+    g_geo.push_back(GeoEntry{dev, L, fp32, x});
+    *g = x;
     return CJT_OK;
 }
 

@@ -394,6 +394,194 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
     if (has_half) Target<K>::finish(d, L / 2, acc[(2 * ept) * nth + tid]);
 }
 
+// ------------------------------------------------------------------ chirp-z (any L)
+//
+// For L not a power of two the length-L complex FFT Z_s = sum_t z_t e^{2 pi i ts/L}
+// uses ts = (t^2 + s^2 - (s-t)^2)/2:  Z_s = c_s (a * b)_s with a_t = z_t c_t,
+// c_t = e^{i pi t^2/L}, b_k = conj(c_|k|), and the linear convolution is a cyclic
+// one of length P >= 2L-1:  a * b = F^-1(F(a) F(b~)),  F^-1(X) = conj(F(conj X))/P.
+// F(b~) is a per-length table.  Per job: two P-point transforms (column + row
+// passes each), then the untangling of the length-2L real DFT from Z.
+//
+// Job storage (complex, per job): [0, P) column-pass output, [P, 2P) first
+// transform in natural order, [2P, 2P+L) Z.
+
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+
+// stage 0: kernel spectrum (input b~ from the chirp table, output to bl)
+// stage 1: input a_t = source(t) c_t, output A (natural order)
+// stage 2: input conj(A_t F(b~)_t), output Z_s = c_s conj(E_s)/P for s < L
+template <typename T, Src S, int STAGE>
+__global__ void __launch_bounds__(256) k_bs_col(const ExecDesc* __restrict__ descs, FftGeom g, int TC, cx<T>* scratch)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+    const int64_t P = g.P, L = g.L;
+    const int P1 = g.L1, P2 = g.L2;
+    const int job = blockIdx.y;
+    const ExecDesc* d = STAGE == 0 ? nullptr : &descs[blockIdx.z];
+    if constexpr (STAGE != 0)
+        if (!Source<S>::valid(*d, job)) return;
+    const int tid = threadIdx.x;
+    const int c = tid % TC, lt = tid / TC;
+    const int64_t col = (int64_t)blockIdx.x * TC + c;
+    const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
+    const cx<T>* chirp = reinterpret_cast<const cx<T>*>(g.chirp);
+    const cx<T>* bl = reinterpret_cast<const cx<T>*>(g.bl);
+    cx<T>* base = STAGE == 0 ? scratch : reinterpret_cast<cx<T>*>(d->tmp) + (int64_t)job * (2 * P + L);
+    const int step = P1 >> 4;
+    cx<T> v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t t = (int64_t)(lt + r * step) * P2 + col;
+        cx<T> x = {(T)0, (T)0};
+        if constexpr (STAGE == 0) {
+            if (t < L) x = conj(chirp[t]);
+            else if (t > P - L) x = conj(chirp[P - t]);
+        } else if constexpr (STAGE == 1) {
+            if (t < L) x = cmul(to_t<T>(Source<S>::load(*d, job, t)), chirp[t]);
+        } else {
+            x = conj(cmul(base[P + t], bl[t]));
+        }
+        v[r] = x;
+    }
+    fft_reg<T>(v, lds + c * slice_stride(P1), g.logL1, lt, true, tw, 2 * P);
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2) {
+        const int64_t k1 = fft_out_index(s2, lt, g.logL1);
+        const int64_t q = (2 * col * k1) & (2 * P - 1);
+        base[k1 * P2 + col] = cmul(v[s2], tw[q]);
+    }
+}
+
+template <typename T, Src S, int STAGE>
+__global__ void __launch_bounds__(256) k_bs_row(const ExecDesc* __restrict__ descs, FftGeom g, int TR, cx<T>* scratch,
+                                                cx<T>* bl_out)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+    const int64_t P = g.P, L = g.L;
+    const int P1 = g.L1, P2 = g.L2;
+    const int job = blockIdx.y;
+    const ExecDesc* d = STAGE == 0 ? nullptr : &descs[blockIdx.z];
+    if constexpr (STAGE != 0)
+        if (!Source<S>::valid(*d, job)) return;
+    const int tid = threadIdx.x;
+    const int tpr = P2 >> 4;
+    const int rr = tid / tpr, lt = tid - rr * tpr;
+    const int64_t k1 = (int64_t)blockIdx.x * TR + rr;
+    const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
+    const cx<T>* chirp = reinterpret_cast<const cx<T>*>(g.chirp);
+    cx<T>* base = STAGE == 0 ? scratch : reinterpret_cast<cx<T>*>(d->tmp) + (int64_t)job * (2 * P + L);
+    cx<T> v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = base[k1 * P2 + lt + r * tpr];
+    fft_reg<T>(v, lds + rr * slice_stride(P2), g.logL2, lt, true, tw, 2 * P);
+    const T invP = (T)1 / (T)P;
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2) {
+        const int64_t k2 = fft_out_index(s2, lt, g.logL2);
+        const int64_t sidx = k1 + (int64_t)P1 * k2;
+        if constexpr (STAGE == 0) bl_out[sidx] = v[s2];
+        else if constexpr (STAGE == 1) base[P + sidx] = v[s2];
+        else if (sidx < L) base[2 * P + sidx] = cmul(chirp[sidx], cscale(conj(v[s2]), invP));
+    }
+}
+
+// Untangling of the length-2L real DFT from Z, summed over the jobs of the
+// instance (terms m outer, blocks k inner); one element (s, L-s) per thread.
+template <typename T, Sink K>
+__global__ void __launch_bounds__(256) k_bs_untangle(const ExecDesc* __restrict__ descs, FftGeom g, int single_job)
+{
+    const ExecDesc& d = descs[blockIdx.y];
+    const int64_t L = g.L, P = g.P;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > L / 2) return;
+    const cx<T>* utw = reinterpret_cast<const cx<T>*>(g.utw);
+    const int njobs = single_job ? 1 : d.nblk * d.M;
+    double a0 = 0.0, a1 = 0.0;
+    for (int it = 0; it < njobs; ++it) {
+        const int job = single_job ? 0 : (it % d.nblk) * d.M + it / d.nblk;
+        const cx<T>* Z = reinterpret_cast<const cx<T>*>(d.tmp) + (int64_t)job * (2 * P + L) + 2 * P;
+        cx<double> xa, xb;
+        if (s == 0) {
+            const cx<T> z = Z[0];
+            xa = {(double)z.re + (double)z.im, 0.0};
+            xb = {(double)z.re - (double)z.im, 0.0};
+        } else if (2 * s == L) {
+            const cx<T> z = Z[s];
+            xa = {(double)z.re, (double)z.im};
+            xb = xa;
+        } else {
+            untangle<T>(Z[s], Z[L - s], utw[s], xa, xb);
+        }
+        a0 += Target<K>::contrib(d, job, s, xa);
+        if (2 * s != L) a1 += Target<K>::contrib(d, job, L - s, xb);
+    }
+    Target<K>::finish(d, s, a0);
+    if (2 * s != L) Target<K>::finish(d, L - s, a1);
+}
+
+// Whole chirp-z transform in one workgroup (P <= kSingleMax), looping over the jobs.
+template <typename T, Src S, Sink K>
+__global__ void __launch_bounds__(256) k_bs_single(const ExecDesc* __restrict__ descs, FftGeom g, int max_jobs,
+                                                   size_t acc_off)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const ExecDesc& d = descs[blockIdx.x];
+    const int L = (int)g.L, P = (int)g.P;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
+    const cx<T>* chirp = reinterpret_cast<const cx<T>*>(g.chirp);
+    const cx<T>* bl = reinterpret_cast<const cx<T>*>(g.bl);
+    const cx<T>* utw = reinterpret_cast<const cx<T>*>(g.utw);
+    const int nel = L / 2 + 1;
+    double* acc = reinterpret_cast<double*>(smem_raw + acc_off);
+    for (int i = 0; i < kSlots; ++i) acc[i * nth + tid] = 0.0;
+    const T invP = (T)1 / (T)P;
+    for (int job = 0; job < max_jobs; ++job) {
+        if (!Source<S>::valid(d, job)) break;
+        for (int t = tid; t < P; t += nth)
+            buf[lds_pad(t)] = t < L ? cmul(to_t<T>(Source<S>::load(d, job, t)), chirp[t]) : cx<T>{(T)0, (T)0};
+        __syncthreads();
+        lds_fft<T>(buf, g.logP, 1, tw, 2 * g.P);
+        for (int t = tid; t < P; t += nth) buf[lds_pad(t)] = conj(cmul(buf[lds_pad(t)], bl[t]));
+        __syncthreads();
+        lds_fft<T>(buf, g.logP, 1, tw, 2 * g.P);
+        for (int t = tid; t < L; t += nth) buf[lds_pad(t)] = cmul(chirp[t], cscale(conj(buf[lds_pad(t)]), invP));
+        __syncthreads();
+#pragma unroll 2
+        for (int q = 0; q < kSlots / 2; ++q) {
+            const int sx = tid + q * nth;
+            if (sx >= nel) break;
+            cx<double> xa, xb;
+            if (sx == 0) {
+                cx<T> z = buf[lds_pad(0)];
+                xa = {(double)z.re + (double)z.im, 0.0};
+                xb = {(double)z.re - (double)z.im, 0.0};
+            } else if (2 * sx == L) {
+                cx<T> z = buf[lds_pad(sx)];
+                xa = {(double)z.re, (double)z.im};
+                xb = xa;
+            } else {
+                untangle<T>(buf[lds_pad(sx)], buf[lds_pad(L - sx)], utw[sx], xa, xb);
+            }
+            acc[(2 * q) * nth + tid] += Target<K>::contrib(d, job, sx, xa);
+            if (2 * sx != L) acc[(2 * q + 1) * nth + tid] += Target<K>::contrib(d, job, L - sx, xb);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < kSlots / 2; ++q) {
+        const int sx = tid + q * nth;
+        if (sx >= nel) break;
+        Target<K>::finish(d, sx, acc[(2 * q) * nth + tid]);
+        if (2 * sx != L) Target<K>::finish(d, L - sx, acc[(2 * q + 1) * nth + tid]);
+    }
+}
+
 // ------------------------------------------------------------------ launch
 
 namespace {
@@ -411,6 +599,63 @@ cjt_status allow_lds(K kernel, size_t bytes)
 }
 
 template <typename T, Src S, Sink K>
+cjt_status run_bs(const EngineArgs& a, int max_jobs, bool single_job)
+{
+    const FftGeom& g = a.geom;
+    const size_t esz = sizeof(cx<T>);
+    if (g.single) {
+        const int P = (int)g.P;
+        int nth = P / 16;
+        if (nth < 64) nth = 64;
+        if (nth > 256) nth = 256;
+        if (((int)g.L / 2 + 1 + nth - 1) / nth > kSlots / 2) return fail(CJT_EUNSUPPORTED, "chirp-z length too large");
+        const size_t acc_off = (lds_bytes(P, esz) + 255) & ~(size_t)255;
+        const size_t total = acc_off + sizeof(double) * kSlots * nth;
+        cjt_status st = allow_lds(k_bs_single<T, S, K>, total);
+        if (st != CJT_OK) return st;
+        ProfScope ps(a.name1, a.flops1 + a.flops2, a.bytes1 + a.bytes2, a.stream);
+        hipLaunchKernelGGL((k_bs_single<T, S, K>), dim3(a.count), dim3(nth), total, a.stream, a.d_desc, g, max_jobs,
+                           acc_off);
+        CJT_HIP_TRY(hipGetLastError());
+        return CJT_OK;
+    }
+    const int TC = std::max(1, 2048 / g.L1);
+    const int TR = std::max(1, 2048 / g.L2);
+    const int nth1 = TC * (g.L1 / 16), nth2 = TR * (g.L2 / 16);
+    if (g.L2 % TC != 0 || g.L1 % TR != 0 || nth1 > 256 || nth2 > 256) return fail(CJT_EUNSUPPORTED, "chirp-z split");
+    const size_t lds1 = (size_t)TC * slice_stride(g.L1) * esz, lds2 = (size_t)TR * slice_stride(g.L2) * esz;
+    cjt_status st = allow_lds(k_bs_col<T, S, 1>, lds1);
+    if (st == CJT_OK) st = allow_lds(k_bs_col<T, S, 2>, lds1);
+    if (st == CJT_OK) st = allow_lds(k_bs_row<T, S, 1>, lds2);
+    if (st == CJT_OK) st = allow_lds(k_bs_row<T, S, 2>, lds2);
+    if (st != CJT_OK) return st;
+    const dim3 gc(g.L2 / TC, max_jobs, a.count), gr(g.L1 / TR, max_jobs, a.count);
+    {
+        ProfScope ps(a.name1, 0.5 * a.flops1, 0.5 * a.bytes1, a.stream);
+        hipLaunchKernelGGL((k_bs_col<T, S, 1>), gc, dim3(nth1), lds1, a.stream, a.d_desc, g, TC, (cx<T>*)nullptr);
+        CJT_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL((k_bs_row<T, S, 1>), gr, dim3(nth2), lds2, a.stream, a.d_desc, g, TR, (cx<T>*)nullptr,
+                           (cx<T>*)nullptr);
+        CJT_HIP_TRY(hipGetLastError());
+    }
+    {
+        ProfScope ps(a.name1, 0.5 * a.flops1, 0.5 * a.bytes1, a.stream);
+        hipLaunchKernelGGL((k_bs_col<T, S, 2>), gc, dim3(nth1), lds1, a.stream, a.d_desc, g, TC, (cx<T>*)nullptr);
+        CJT_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL((k_bs_row<T, S, 2>), gr, dim3(nth2), lds2, a.stream, a.d_desc, g, TR, (cx<T>*)nullptr,
+                           (cx<T>*)nullptr);
+        CJT_HIP_TRY(hipGetLastError());
+    }
+    {
+        ProfScope ps(a.name2, a.flops2, a.bytes2, a.stream);
+        const dim3 gu((unsigned)((g.L / 2 + 1 + 255) / 256), a.count);
+        hipLaunchKernelGGL((k_bs_untangle<T, K>), gu, dim3(256), 0, a.stream, a.d_desc, g, single_job ? 1 : 0);
+        CJT_HIP_TRY(hipGetLastError());
+    }
+    return CJT_OK;
+}
+
+template <typename T, Src S, Sink K>
 cjt_status run(const EngineArgs& a)
 {
     const FftGeom& g = a.geom;
@@ -418,6 +663,7 @@ cjt_status run(const EngineArgs& a)
     const bool single_job = (S != Src::FwdAsy && S != Src::InvAsy);
     const int max_jobs = single_job ? 1 : a.max_jobs;
     if (max_jobs <= 0 || a.count <= 0) return CJT_OK;
+    if (g.bluestein) return run_bs<T, S, K>(a, max_jobs, single_job);
     if (g.single) {
         const int L = (int)g.L;
         int nth = L / 16;
@@ -476,6 +722,132 @@ cjt_status launch_rdft(const EngineArgs& a, Src src, Sink sink, bool fp32)
     if (src == Src::InvInit && sink == Sink::InvInit) return run<double, Src::InvInit, Sink::InvInit>(a);
     if (src == Src::Moments && sink == Sink::Weights) return run<double, Src::Moments, Sink::Weights>(a);
     return fail(CJT_EINVAL, "unknown transform pairing");
+}
+
+// chirp-z tables: c_t = e^{i pi t^2 / L} (t < L), utw_s = e^{i pi s / L} (s <= L)
+template <typename T>
+__global__ void k_chirp_tables(cx<T>* chirp, cx<T>* utw, int64_t L)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > L) return;
+    double sn, cs;
+    if (t < L) {
+        const int64_t r = (t * t) % (2 * L);  // exact angle reduction
+        sincospi((double)r / (double)L, &sn, &cs);
+        chirp[t] = {(T)cs, (T)sn};
+    }
+    sincospi((double)t / (double)L, &sn, &cs);
+    utw[t] = {(T)cs, (T)sn};
+}
+
+template <typename T>
+__global__ void k_to_float(const cx<double>* in, cx<float>* out, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = {(float)in[i].re, (float)in[i].im};
+}
+
+// F(b~) in one workgroup for P <= kSingleMax
+__global__ void __launch_bounds__(256) k_bl_single(FftGeom g, cx<double>* bl)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<double>* buf = reinterpret_cast<cx<double>*>(smem_raw);
+    const int64_t P = g.P, L = g.L;
+    const cx<double>* chirp = reinterpret_cast<const cx<double>*>(g.chirp);
+    const cx<double>* tw = reinterpret_cast<const cx<double>*>(g.tw);
+    for (int64_t t = threadIdx.x; t < P; t += blockDim.x) {
+        cx<double> x = {0.0, 0.0};
+        if (t < L) x = conj(chirp[t]);
+        else if (t > P - L) x = conj(chirp[P - t]);
+        buf[lds_pad((int)t)] = x;
+    }
+    __syncthreads();
+    lds_fft<double>(buf, g.logP, 1, tw, 2 * P);
+    for (int64_t t = threadIdx.x; t < P; t += blockDim.x) bl[t] = buf[lds_pad((int)t)];
+}
+
+// Builds chirp, utw and F(b~) for g (whose L, P, split and tw are set), in FP64
+// and, if fp32, converts them.  Device memory is owned by the caller's cache.
+cjt_status make_chirp_tables(FftGeom* g, bool fp32, hipStream_t st)
+{
+    const int64_t L = g->L, P = g->P;
+    cx<double>* chirp = nullptr;
+    cx<double>* utw = nullptr;
+    cx<double>* bl = nullptr;
+    CJT_HIP_TRY(hipMalloc(&chirp, sizeof(cx<double>) * L));
+    CJT_HIP_TRY(hipMalloc(&utw, sizeof(cx<double>) * (L + 1)));
+    CJT_HIP_TRY(hipMalloc(&bl, sizeof(cx<double>) * P));
+    hipLaunchKernelGGL(k_chirp_tables<double>, dim3((unsigned)((L + 1 + 255) / 256)), dim3(256), 0, st, chirp, utw, L);
+    CJT_HIP_TRY(hipGetLastError());
+    FftGeom g64 = *g;
+    g64.chirp = chirp;
+    g64.utw = utw;
+    const void* tw64 = nullptr;
+    cjt_status s = CJT_OK;
+    if (fp32) {
+        // the kernel spectrum is always formed in FP64
+        s = fft_twiddles_cached(P, false, st, &tw64);
+        if (s != CJT_OK) return s;
+        g64.tw = tw64;
+    }
+    if (g->single) {
+        const size_t lds = lds_bytes((int)P, sizeof(cx<double>));
+        s = allow_lds(k_bl_single, lds);
+        if (s != CJT_OK) return s;
+        hipLaunchKernelGGL(k_bl_single, dim3(1), dim3(256), lds, st, g64, bl);
+        CJT_HIP_TRY(hipGetLastError());
+    } else {
+        cx<double>* scratch = nullptr;
+        CJT_HIP_TRY(hipMalloc(&scratch, sizeof(cx<double>) * P));
+        const int TC = std::max(1, 2048 / g->L1), TR = std::max(1, 2048 / g->L2);
+        const int nth1 = TC * (g->L1 / 16), nth2 = TR * (g->L2 / 16);
+        const size_t lds1 = (size_t)TC * slice_stride(g->L1) * 16, lds2 = (size_t)TR * slice_stride(g->L2) * 16;
+        s = allow_lds(k_bs_col<double, Src::FwdAsy, 0>, lds1);
+        if (s == CJT_OK) s = allow_lds(k_bs_row<double, Src::FwdAsy, 0>, lds2);
+        if (s != CJT_OK) return s;
+        hipLaunchKernelGGL((k_bs_col<double, Src::FwdAsy, 0>), dim3(g->L2 / TC, 1, 1), dim3(nth1), lds1, st,
+                           (const ExecDesc*)nullptr, g64, TC, scratch);
+        CJT_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL((k_bs_row<double, Src::FwdAsy, 0>), dim3(g->L1 / TR, 1, 1), dim3(nth2), lds2, st,
+                           (const ExecDesc*)nullptr, g64, TR, scratch, bl);
+        CJT_HIP_TRY(hipGetLastError());
+        CJT_HIP_TRY(hipStreamSynchronize(st));
+        CJT_HIP_TRY(hipFree(scratch));
+    }
+    if (!fp32) {
+        g->chirp = chirp;
+        g->utw = utw;
+        g->bl = bl;
+    } else {
+        cx<float>* c32 = nullptr;
+        cx<float>* u32 = nullptr;
+        cx<float>* b32 = nullptr;
+        CJT_HIP_TRY(hipMalloc(&c32, sizeof(cx<float>) * L));
+        CJT_HIP_TRY(hipMalloc(&u32, sizeof(cx<float>) * (L + 1)));
+        CJT_HIP_TRY(hipMalloc(&b32, sizeof(cx<float>) * P));
+        hipLaunchKernelGGL(k_to_float<float>, dim3((unsigned)((L + 255) / 256)), dim3(256), 0, st, chirp, c32, L);
+        hipLaunchKernelGGL(k_to_float<float>, dim3((unsigned)((L + 256) / 256)), dim3(256), 0, st, utw, u32, L + 1);
+        hipLaunchKernelGGL(k_to_float<float>, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, bl, b32, P);
+        CJT_HIP_TRY(hipGetLastError());
+        CJT_HIP_TRY(hipStreamSynchronize(st));
+        CJT_HIP_TRY(hipFree(chirp));
+        CJT_HIP_TRY(hipFree(utw));
+        CJT_HIP_TRY(hipFree(bl));
+        g->chirp = c32;
+        g->utw = u32;
+        g->bl = b32;
+    }
+    CJT_HIP_TRY(hipStreamSynchronize(st));
+    return CJT_OK;
+}
+
+size_t fft_job_bytes(int64_t L, bool fp32)
+{
+    const size_t esz = fp32 ? 8 : 16;
+    if ((L & (L - 1)) == 0) return L > kSingleMax ? esz * (size_t)L : 0;
+    int64_t P = 1;
+    while (P < 2 * L - 1) P <<= 1;
+    return P > kSingleMax ? esz * (size_t)(2 * P + L) : 0;
 }
 
 // tw[q] = exp(i pi q / L), q < 2L

@@ -20,9 +20,101 @@
 // Each thread carries kPPT points; per 16 degrees the wave sums its 64*kPPT
 // values per degree through LDS and writes one partial sum per task and
 // degree; a second kernel adds the partials of all tasks in a fixed order.
+//
+// Evaluation points.  P_n(cos theta) oscillates with frequency n in theta, so a
+// point rounded to FP64 (relative error eps in theta or in x -+ 1) shifts
+// P_n by about eps n theta, the same sign for every degree: near the ends,
+// where the recurrence runs up to degree N, that systematic error dominates.
+// Each point is therefore carried as a double-double x_hi + x_lo (or
+// (x - x0)_hi + (x - x0)_lo), built from the exact rational angle, and every
+// step forms A_n x u as A_n (x_hi u + x_lo u): rounding the linear factor
+// A_n x + B_n to FP64 first would act like a rounded point again (it costs
+// about a factor 10 in the inverse when the recurrence covers the whole
+// matrix).  What remains is the per-step rounding of the recurrence itself.
 #include "cjt_internal.h"
 
 namespace cjt {
+
+// ------------------------------------------------------------------ points
+
+namespace {
+
+struct ddv {
+    double hi, lo;
+};
+
+__device__ __forceinline__ ddv fast_two_sum(double a, double b)
+{
+#pragma clang fp contract(off)
+    const double s = a + b;
+    return {s, b - (s - a)};
+}
+
+__device__ __forceinline__ ddv dd_add(ddv a, ddv b)
+{
+#pragma clang fp contract(off)
+    const double s = a.hi + b.hi;
+    const double bb = s - a.hi;
+    const double e = (a.hi - (s - bb)) + (b.hi - bb);
+    return fast_two_sum(s, e + a.lo + b.lo);
+}
+
+__device__ __forceinline__ ddv dd_mul(ddv a, ddv b)
+{
+#pragma clang fp contract(off)
+    const double p = a.hi * b.hi;
+    const double e = fma(a.hi, b.hi, -p);
+    return fast_two_sum(p, fma(a.hi, b.lo, fma(a.lo, b.hi, e)));
+}
+
+// a / m for an integer m < 2^53
+__device__ __forceinline__ ddv dd_div(ddv a, double m)
+{
+#pragma clang fp contract(off)
+    const double q = a.hi / m;
+    const double r = fma(-q, m, a.hi) + a.lo;
+    return fast_two_sum(q, r / m);
+}
+
+// sin(pi num / den) for integers |num| <= den / 4, den < 2^53, in double-double:
+// the ratio is formed exactly, multiplied by pi (double-double), and the
+// Taylor series is summed by Horner's rule, 14 terms (the first omitted term
+// is below 1e-33 of the result for |angle| <= pi/4).
+__device__ ddv sinpi_ratio(double num, double den)
+{
+#pragma clang fp contract(off)
+    const double fh = num / den;
+    const ddv f = fast_two_sum(fh, fma(-fh, den, num) / den);
+    const ddv pi = {3.141592653589793116e+00, 1.2246467991473532072e-16};
+    const ddv a = dd_mul(pi, f);
+    const ddv a2 = dd_mul(a, a);
+    ddv s = {1.0, 0.0};
+    for (int k = 13; k >= 1; --k) {
+        const ddv t = dd_div(dd_mul(a2, s), (double)(2 * k) * (double)(2 * k + 1));
+        s = dd_add(ddv{1.0, 0.0}, ddv{-t.hi, -t.lo});
+    }
+    return dd_mul(a, s);
+}
+
+// Point i of the grid theta_i = pi i / G: x_i (mode 0, pi/4 <= theta <= 3pi/4),
+// x_i - 1 = -2 sin^2(theta/2) (mode +1) or x_i + 1 = 2 sin^2((pi - theta)/2)
+// (mode -1), as hi + lo.
+__device__ void grid_point(int64_t i, int64_t G, int mode, double& hi, double& lo)
+{
+    ddv v;
+    if (mode == 0) {
+        v = sinpi_ratio((double)(G - 2 * i), (double)(2 * G));
+    } else {
+        const ddv sh = sinpi_ratio((double)(mode > 0 ? i : G - i), (double)(2 * G));
+        v = dd_mul(sh, sh);
+        const double sc = mode > 0 ? -2.0 : 2.0;
+        v = {v.hi * sc, v.lo * sc};
+    }
+    hi = v.hi;
+    lo = v.lo;
+}
+
+}  // namespace
 
 constexpr int kPPT = 4;     // points per thread, inverse
 constexpr int kChunk = 16;  // degrees per LDS reduction round (divides kBlk)
@@ -87,19 +179,11 @@ __global__ void __launch_bounds__(64) k_rec_fwd(const ExecDesc* __restrict__ des
     const double* __restrict__ c = d.in;
     const d4* __restrict__ co = mode == 0 ? d.rec0 : (mode > 0 ? d.recp : d.recm);
     // plain: (A_n, B_n, C_{n+1});  modified: (A_n, C_{n+1} r_{n+1}, 1/r_n)
-    double xv[kPPTF], s1[kPPTF], s2[kPPTF];
-#pragma unroll
+    double xh[kPPTF], xl[kPPTF], s1[kPPTF], s2[kPPTF];
     for (int q = 0; q < kPPTF; ++q) {
         const int idx = lane + 64 * q;
         const int64_t i = p0 + (idx < np ? idx : 0);
-        if (mode == 0) {
-            double sn;
-            sincospi((double)i / (double)N, &sn, &xv[q]);
-        } else {
-            double sh, ch;
-            sincospi((double)i / (double)(2 * N), &sh, &ch);
-            xv[q] = mode > 0 ? -2.0 * sh * sh : 2.0 * ch * ch;
-        }
+        grid_point(i, N, mode, xh[q], xl[q]);
         s1[q] = 0.0;  // plain: u_{n+1};  modified: u_{n+1}
         s2[q] = 0.0;  // plain: u_{n+2};  modified: D_{n+1}
     }
@@ -124,7 +208,8 @@ __global__ void __launch_bounds__(64) k_rec_fwd(const ExecDesc* __restrict__ des
                 const double cn = S.c[t];
 #pragma unroll
                 for (int q = 0; q < kPPTF; ++q) {
-                    const double u0 = fma(fma(q4.x, xv[q], q4.y), s1[q], fma(-q4.z, s2[q], cn));
+                    const double w = fma(xh[q], s1[q], xl[q] * s1[q]);
+                    const double u0 = fma(q4.x, w, fma(q4.y, s1[q], fma(-q4.z, s2[q], cn)));
                     s2[q] = s1[q];
                     s1[q] = u0;
                 }
@@ -137,7 +222,8 @@ __global__ void __launch_bounds__(64) k_rec_fwd(const ExecDesc* __restrict__ des
                 const bool last = (b0 + t) == 0;
 #pragma unroll
                 for (int q = 0; q < kPPTF; ++q) {
-                    const double Dn = fma(q4.x * xv[q], s1[q], fma(q4.y, s2[q], cn));
+                    const double w = fma(xh[q], s1[q], xl[q] * s1[q]);
+                    const double Dn = fma(q4.x, w, fma(q4.y, s2[q], cn));
                     if (!last) s1[q] = fma(s1[q], q4.z, Dn);
                     s2[q] = Dn;
                 }
@@ -179,8 +265,7 @@ __global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ des
     const int64_t G = d.G;
     double* __restrict__ part = d.part + off;
 
-    double pv[kPPT], ev[kPPT], xv[kPPT];
-#pragma unroll
+    double pv[kPPT], ev[kPPT], xh[kPPT], xl[kPPT];
     for (int q = 0; q < kPPT; ++q) {
         const int idx = lane + 64 * q;
         const bool act = idx < np;
@@ -188,15 +273,7 @@ __global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ des
         const double g = act ? d.p[j] : 0.0;
         pv[q] = g;      // pi_0 = g_j (scaled recurrence)
         ev[q] = 0.0;    // e_0 = 0 (modified) / P_{-1} = 0 (three-term)
-        if (mode == 0) {
-            double s, x;
-            sincospi((double)j / (double)G, &s, &x);
-            xv[q] = x;
-        } else {
-            double sh, ch;
-            sincospi((double)j / (double)(2 * G), &sh, &ch);
-            xv[q] = mode > 0 ? -2.0 * sh * sh : 2.0 * ch * ch;
-        }
+        grid_point(j, G, mode, xh[q], xl[q]);
     }
     // three-term: (A_n, B_n, C_n);  modified: (A_n, C_n / r_{n-1}, r_n)
     const d4* __restrict__ co = mode == 0 ? d.rec0 : (mode > 0 ? d.recp : d.recm);
@@ -226,14 +303,16 @@ __global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ des
                 if (mode == 0) {
 #pragma unroll
                     for (int q = 0; q < kPPT; ++q) {
-                        const double p1 = fma(fma(cf.x, xv[q], cf.y), pv[q], -cf.z * ev[q]);
+                        const double w = fma(xh[q], pv[q], xl[q] * pv[q]);
+                        const double p1 = fma(cf.x, w, fma(cf.y, pv[q], -cf.z * ev[q]));
                         ev[q] = pv[q];
                         pv[q] = p1;
                     }
                 } else {
 #pragma unroll
                     for (int q = 0; q < kPPT; ++q) {
-                        const double e1 = fma(cf.x * xv[q], pv[q], cf.y * ev[q]);
+                        const double w = fma(xh[q], pv[q], xl[q] * pv[q]);
+                        const double e1 = fma(cf.x, w, cf.y * ev[q]);
                         pv[q] = fma(pv[q], cf.z, e1);
                         ev[q] = e1;
                     }

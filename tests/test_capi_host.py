@@ -33,7 +33,7 @@ def test_exports_match_header(lib):
 
 
 @pytest.mark.parametrize("args,status", [
-    ((1000, 0.1, 0.1, 0), "CJT_EUNSUPPORTED"),
+    (((1 << 21) + 1, 0.1, 0.1, 0), "CJT_EUNSUPPORTED"),
     ((0, 0.1, 0.1, 0), "CJT_EINVAL"),
     ((1024, 0.6, 0.1, 0), "CJT_EDOMAIN"),
     ((1024, -0.5, 0.1, 0), "CJT_EDOMAIN"),

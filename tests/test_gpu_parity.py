@@ -125,6 +125,35 @@ def test_hahn_terms(lib, oracle_mod, M):
     assert ef <= tol(N) and eg <= tol(N)
 
 
+@pytest.mark.parametrize("N", [3, 5, 7, 100, 1000, 1023, 2049, 3000, 5000, 12345])
+def test_sizes_any_length(lib, oracle_mod, N):
+    """Lengths that are not powers of two: the DCT-I/DST-I behind every block go
+    through the chirp-z convolution (one workgroup up to P = 4096, two passes above)."""
+    rng = np.random.default_rng(300 + N)
+    a, b = float(rng.uniform(-0.5, 0.5)), float(rng.uniform(-0.5, 0.5))
+    c = inputs.decaying_coeffs(rng, N, 1.0)
+    f_ref, g_ref = oracle_pair(oracle_mod, c, a, b)
+    f, plan = run_fwd(lib, c, a, b)
+    g, _ = run_inv(lib, c, a, b)
+    ef, eg = rel2(f, f_ref), rel2(g, g_ref)
+    print(f"N={N} a={a:.3f} b={b:.3f} M={plan.info.M} kf={plan.info.fwd.nblocks} ki={plan.info.inv.nblocks} "
+          f"fwd {ef:.2e} inv {eg:.2e}")
+    assert ef <= tol(N)
+    assert eg <= tol(N)
+
+
+def test_any_length_exact_case(lib, oracle_mod):
+    """alpha = beta = 1/2 at an odd length: one exact Hahn term over the whole interior."""
+    N = 999
+    c = inputs.decaying_coeffs(np.random.default_rng(5), N, 1.0)
+    f_ref, g_ref = oracle_pair(oracle_mod, c, 0.5, 0.5)
+    f, plan = run_fwd(lib, c, 0.5, 0.5)
+    g, _ = run_inv(lib, c, 0.5, 0.5)
+    ef, eg = rel2(f, f_ref), rel2(g, g_ref)
+    print(f"N={N} exact case M={plan.info.M} fwd {ef:.2e} inv {eg:.2e}")
+    assert ef <= tol(N) and eg <= tol(N)
+
+
 def test_fp32_bulk_error_reported(lib, oracle_mod):
     """FP32 Hahn-block FFTs: no bound in the paper (parity unpinned); the error is
     measured and must stay at single-precision level."""
@@ -142,7 +171,7 @@ def test_batched_mixed(lib, oracle_mod):
     """Ragged batch: different N and (alpha, beta) per instance, repeated plan."""
     import torch
     rng = np.random.default_rng(11)
-    Ns = [1024, 64, 8192, 1024, 2, 4096]
+    Ns = [1024, 64, 8192, 1024, 2, 4096, 1000, 3001]
     params = [(float(rng.uniform(-0.5, 0.5)), float(rng.uniform(-0.5, 0.5))) for _ in Ns]
     params[3] = params[0]
     cs = [inputs.decaying_coeffs(rng, N, 1.0) for N in Ns]
@@ -167,8 +196,8 @@ def test_batched_mixed(lib, oracle_mod):
 def test_errors_returned(lib):
     import torch
     with pytest.raises(lib.CJTError) as e:
-        lib.cjt_plan(1000, 0.1, 0.1)
-    assert e.value.status == lib.CJT_EUNSUPPORTED
+        lib.cjt_plan(0, 0.1, 0.1)
+    assert e.value.status == lib.CJT_EINVAL
     with pytest.raises(lib.CJTError) as e:
         lib.cjt_plan(1024, 0.6, 0.1)
     assert e.value.status == lib.CJT_EDOMAIN
