@@ -41,6 +41,7 @@ extern "C" {
 #endif
 
 typedef struct cjt_plan_s* cjt_plan_t;
+typedef struct cjt_batch_s* cjt_batch_t;
 
 typedef enum {
     CJT_OK = 0,
@@ -57,6 +58,12 @@ enum {
     CJT_FP64 = 0,          /* every step in FP64 */
     CJT_FP32_BULK = 1      /* the DCT-I/DST-I of the Hahn blocks in FP32 with FP32 accumulation;
                               diagonals, recurrences and boundary DCTs stay FP64 */
+};
+
+/* Direction flags of a persistent batch. */
+enum {
+    CJT_DIR_FWD = 2,       /* forward transforms (eq. CJT) */
+    CJT_DIR_INV = 4        /* inverse transforms (eq. CJTT) */
 };
 
 #define CJT_MAX_BLOCKS 16
@@ -116,11 +123,39 @@ cjt_status cjt_inverse(cjt_plan_t plan, const double* d_in, double* d_out, void*
  * d_in[offsets[i] .. offsets[i+1]) and d_out[same], where offsets is a host
  * array of count+1 entries with offsets[i+1] - offsets[i] = N_i + 1.  All
  * plans must share one precision flag.  One launch sequence serves the whole
- * batch. */
+ * batch, whatever the mix of degrees: each kernel runs over a flat list of
+ * work items of all instances. */
 cjt_status cjt_forward_batched(const cjt_plan_t* plans, int64_t count, const int64_t* offsets,
                                const double* d_in, double* d_out, void* stream);
 cjt_status cjt_inverse_batched(const cjt_plan_t* plans, int64_t count, const int64_t* offsets,
                                const double* d_in, double* d_out, void* stream);
+
+/* Persistent batch (Sec. 4: many sets of coefficients, one plan each).
+ * cjt_batch_create does all host-side work once: it lays out the launch
+ * program for `count` transforms (plans[i], ragged slices given by the host
+ * array offsets as in cjt_forward_batched; flags = CJT_DIR_FWD or
+ * CJT_DIR_INV), allocates the batch's own device workspace (FFT
+ * intermediates of every instance at once, so no chunking), and uploads the
+ * descriptors and work items; it returns when they are resident.  The plans
+ * must outlive the batch.  cjt_batch_execute only launches kernels on
+ * `stream` and on a stream the batch owns (joined back before it returns), so
+ * a call can be captured into a HIP graph and replayed; d_in / d_out are
+ * the base pointers of the ragged arrays (any pointers on each call).  Calls
+ * on one batch must not overlap in time: they share its workspace. */
+typedef struct {
+    int64_t count;            /* transforms */
+    int64_t launches;         /* kernel launches per execution (plus stream fork/join) */
+    int64_t items;            /* work items over all launches */
+    size_t workspace_bytes;   /* device memory held by the batch besides descriptors */
+    int32_t inverse;          /* 1 for CJT_DIR_INV */
+} cjt_batch_info;
+
+cjt_status cjt_batch_create(cjt_batch_t* out, const cjt_plan_t* plans, int64_t count, const int64_t* offsets,
+                            unsigned flags, void* stream);
+cjt_status cjt_batch_execute(cjt_batch_t batch, const double* d_in, double* d_out, void* stream);
+cjt_status cjt_batch_query(cjt_batch_t batch, cjt_batch_info* out);
+/* Release a batch (waits for the device). NULL is accepted. */
+cjt_status cjt_batch_destroy(cjt_batch_t batch);
 
 /* Describe a plan (host memory out). */
 cjt_status cjt_plan_query(cjt_plan_t plan, cjt_plan_info* out);

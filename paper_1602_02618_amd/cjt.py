@@ -18,12 +18,15 @@ LIB_PATH = os.path.join(_HERE, "libcjt_hip.so")
 CJT_OK, CJT_EINVAL, CJT_EDOMAIN, CJT_ENOMEM, CJT_EDEVICE, CJT_EBUSY, CJT_EUNSUPPORTED = range(7)
 CJT_FP64 = 0
 CJT_FP32_BULK = 1
+CJT_DIR_FWD = 2
+CJT_DIR_INV = 4
 CJT_MAX_BLOCKS = 16
 
 _EXPORTS = (
     "cjt_plan", "cjt_forward", "cjt_inverse", "cjt_forward_batched", "cjt_inverse_batched",
     "cjt_plan_query", "cjt_plan_describe", "cjt_plan_destroy", "cjt_strerror", "cjt_last_error",
     "cjt_version", "cjt_profile_enable", "cjt_profile_collect",
+    "cjt_batch_create", "cjt_batch_execute", "cjt_batch_query", "cjt_batch_destroy",
 )
 
 
@@ -76,6 +79,16 @@ class cjt_plan_info(ctypes.Structure):
     ]
 
 
+class cjt_batch_info(ctypes.Structure):
+    _fields_ = [
+        ("count", ctypes.c_int64),
+        ("launches", ctypes.c_int64),
+        ("items", ctypes.c_int64),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("inverse", ctypes.c_int32),
+    ]
+
+
 class CJTError(RuntimeError):
     def __init__(self, status, what):
         self.status = status
@@ -115,8 +128,13 @@ def load(path=LIB_PATH):
         lib.cjt_profile_enable.restype = ci
         lib.cjt_profile_collect.argtypes = [P(cjt_kernel_stat), ci, P(ci)]
         lib.cjt_profile_collect.restype = ci
+        lib.cjt_batch_create.argtypes = [P(vp), P(vp), i64, P(i64), cu, vp]
+        lib.cjt_batch_execute.argtypes = [vp, vp, vp, vp]
+        lib.cjt_batch_query.argtypes = [vp, P(cjt_batch_info)]
+        lib.cjt_batch_destroy.argtypes = [vp]
         for f in ("cjt_plan", "cjt_forward", "cjt_inverse", "cjt_forward_batched", "cjt_inverse_batched",
-                  "cjt_plan_query", "cjt_plan_describe", "cjt_plan_destroy"):
+                  "cjt_plan_query", "cjt_plan_describe", "cjt_plan_destroy", "cjt_batch_create",
+                  "cjt_batch_execute", "cjt_batch_query", "cjt_batch_destroy"):
             getattr(lib, f).restype = ci
         _lib = lib
         return lib
@@ -217,6 +235,52 @@ def cjt_forward_batched(plans, offsets, d_in, d_out, stream=None):
 
 def cjt_inverse_batched(plans, offsets, d_in, d_out, stream=None):
     _batched(load().cjt_inverse_batched, "cjt_inverse_batched", plans, offsets, d_in, d_out, stream)
+
+
+class Batch:
+    """Owning wrapper of a cjt_batch_t; keeps its plans alive."""
+
+    def __init__(self, handle, plans):
+        self.handle = handle
+        self.plans = list(plans)
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def destroy(self):
+        if self.handle:
+            h, self.handle = self.handle, None
+            load().cjt_batch_destroy(h)
+
+    @property
+    def info(self):
+        return cjt_batch_query(self)
+
+
+def cjt_batch_create(plans, offsets, flags, stream=None):
+    n = len(plans)
+    arr = (ctypes.c_void_p * max(n, 1))(*[p.handle for p in plans])
+    offs = (ctypes.c_int64 * (n + 1))(*[int(o) for o in offsets])
+    h = ctypes.c_void_p()
+    _check(load().cjt_batch_create(ctypes.byref(h), arr, n, offs, int(flags), _stream(stream)), "cjt_batch_create")
+    return Batch(h.value, plans)
+
+
+def cjt_batch_execute(batch, d_in, d_out, stream=None):
+    _check(load().cjt_batch_execute(batch.handle, _ptr(d_in), _ptr(d_out), _stream(stream)), "cjt_batch_execute")
+
+
+def cjt_batch_query(batch):
+    info = cjt_batch_info()
+    _check(load().cjt_batch_query(batch.handle, ctypes.byref(info)), "cjt_batch_query")
+    return info
+
+
+def cjt_batch_destroy(batch):
+    batch.destroy()
 
 
 def cjt_plan_query(plan):

@@ -15,10 +15,25 @@
 #include <vector>
 
 #include "cjt_internal.h"
+#include "exec.h"
 #include "plan.h"
 
 struct cjt_plan_s {
     cjt::Plan p;
+};
+
+// A persistent batch: the launch program, its descriptors and work items
+// resident on the device, and its own workspace; executing it only launches
+// kernels, so it can be captured into a HIP graph.
+struct cjt_batch_s {
+    int device = 0;
+    bool inverse = false;
+    cjt::Built b;
+    void* ws = nullptr;
+    char* meta = nullptr;  // descriptors, then items
+    size_t dbytes = 0;
+    hipStream_t aux = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace cjt {
@@ -100,9 +115,9 @@ struct Workspace {
     size_t bytes = 0;
     hipStream_t aux = nullptr;    // second stream for the recurrence kernels (default priority)
     hipEvent_t fork = nullptr, join = nullptr;
-    ExecDesc* d_desc = nullptr;
-    size_t desc_cap = 0;
-    ExecDesc* h_desc = nullptr;   // pinned staging
+    char* d_meta = nullptr;       // descriptors and work items on the device
+    char* h_meta = nullptr;       // pinned staging of the same
+    size_t meta_cap = 0;
     hipEvent_t copied = nullptr;  // staging buffer free once this completes
     bool pending = false;
 };
@@ -121,7 +136,7 @@ size_t ws_limit()
     return lim;
 }
 
-cjt_status ws_reserve(Workspace& w, size_t bytes, size_t ndesc, hipStream_t st)
+cjt_status ws_reserve(Workspace& w, size_t bytes, size_t meta, hipStream_t st)
 {
     if (w.pending) {
         CJT_HIP_TRY(hipEventSynchronize(w.copied));
@@ -135,18 +150,18 @@ cjt_status ws_reserve(Workspace& w, size_t bytes, size_t ndesc, hipStream_t st)
         if (hipMalloc(&w.dev, bytes) != hipSuccess) return fail(CJT_ENOMEM, "workspace allocation failed");
         w.bytes = bytes;
     }
-    if (ndesc > w.desc_cap) {
+    if (meta > w.meta_cap) {
         CJT_HIP_TRY(hipStreamSynchronize(st));
-        if (w.d_desc) CJT_HIP_TRY(hipFree(w.d_desc));
-        if (w.h_desc) CJT_HIP_TRY(hipHostFree(w.h_desc));
-        w.d_desc = nullptr;
-        w.h_desc = nullptr;
-        w.desc_cap = 0;
-        size_t cap = std::max<size_t>(ndesc, 64);
-        if (hipMalloc(&w.d_desc, cap * sizeof(ExecDesc)) != hipSuccess) return fail(CJT_ENOMEM, "descriptor buffer");
-        if (hipHostMalloc((void**)&w.h_desc, cap * sizeof(ExecDesc), hipHostMallocDefault) != hipSuccess)
+        if (w.d_meta) CJT_HIP_TRY(hipFree(w.d_meta));
+        if (w.h_meta) CJT_HIP_TRY(hipHostFree(w.h_meta));
+        w.d_meta = nullptr;
+        w.h_meta = nullptr;
+        w.meta_cap = 0;
+        const size_t cap = std::max<size_t>(meta + meta / 2, 1 << 16);
+        if (hipMalloc((void**)&w.d_meta, cap) != hipSuccess) return fail(CJT_ENOMEM, "descriptor buffer");
+        if (hipHostMalloc((void**)&w.h_meta, cap, hipHostMallocDefault) != hipSuccess)
             return fail(CJT_ENOMEM, "descriptor staging buffer");
-        w.desc_cap = cap;
+        w.meta_cap = cap;
     }
     if (!w.copied) CJT_HIP_TRY(hipEventCreateWithFlags(&w.copied, hipEventDisableTiming));
     if (!w.aux) CJT_HIP_TRY(hipStreamCreateWithFlags(&w.aux, hipStreamNonBlocking));
@@ -155,279 +170,50 @@ cjt_status ws_reserve(Workspace& w, size_t bytes, size_t ndesc, hipStream_t st)
     return CJT_OK;
 }
 
-// Zero a vector without hipMemset (kept free of memset nodes for graph capture).
-__global__ void k_zero_out(const ExecDesc* __restrict__ descs)
-{
-    const ExecDesc& d = descs[blockIdx.y];
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n <= d.N) d.out[n] = 0.0;
-}
-
-struct Inst {
-    const Plan* P;
-    const double* in;
-    double* out;
-};
-
-// Per-instance workspace needs (bytes), split by use: p, p2 and part live for
-// the whole call (all instances at once), tmp only for the instance's chunk.
-struct Need {
-    size_t p, p2, part, tmp;
-};
-
-Need need_of(const Plan& P, bool inverse, bool fp32)
-{
-    const Part& pt = inverse ? P.inv : P.fwd;
-    const int64_t L = inverse ? 2 * P.N : P.N;
-    Need n;
-    n.p = sizeof(double) * (size_t)(inverse ? 2 * P.N + 1 : P.N + 1);
-    n.p2 = inverse ? 0 : sizeof(double) * (size_t)(P.N + 1);
-    n.part = inverse ? sizeof(double) * (size_t)std::max<int64_t>(1, P.part_total_i) : 0;
-    const int64_t jobs = (int64_t)pt.nblk * pt.M;
-    n.tmp = (size_t)std::max<int64_t>(jobs, 1) * fft_job_bytes(L, fp32);
-    // the boundary DCTs (FP64) may need an intermediate as well
-    n.tmp = std::max(n.tmp, fft_job_bytes(L, false));
-    return n;
-}
-
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Timing labels of an engine launch; the work is split between the column and
-// row passes in proportion to their FFT stages (half each) for two-pass
-// lengths, and all to the single pass otherwise.
-void label(EngineArgs& ea, const char* n1, const char* n2, double flops, double bytes)
+cjt_status check_batch(const std::vector<const Plan*>& plans)
 {
-    ea.name1 = n1;
-    ea.name2 = n2;
-    ea.flops1 = 0.5 * flops;
-    ea.flops2 = 0.5 * flops;
-    ea.bytes1 = 0.5 * bytes;
-    ea.bytes2 = 0.5 * bytes;
-}
-
-// Algorithmic work of one transform's kernels (see cjt_profile_enable).
-struct Work {
-    double rec_flops = 0, asy_flops = 0, bnd_flops = 0;
-    double rec_bytes = 0, asy_bytes = 0, bnd_bytes = 0;
-};
-
-Work work_of(const Plan& P, bool inverse)
-{
-    Work w;
-    const Part& pt = inverse ? P.inv : P.fwd;
-    const std::vector<RecTask>& tasks = inverse ? P.tasks_i : P.tasks_f;
-    for (const RecTask& t : tasks) w.rec_flops += (double)t.np * (double)t.cut * (t.mode == 0 ? 6.0 : 10.0);
-    const double N = (double)P.N, Lr = inverse ? 4.0 * N : 2.0 * N;  // real FFT length
-    const double fft = 2.5 * Lr * log2(Lr);
-    for (int k = 0; k < pt.nblk; ++k) {
-        const double wk = (double)(pt.win_hi[k] - pt.win_lo[k] + 1), dk = (double)(pt.deg_hi[k] - pt.deg_lo[k]);
-        w.asy_flops += pt.M * (fft + 4.0 * wk + 2.0 * dk);
-    }
-    w.bnd_flops = fft + Lr / 2;
-    const double gN = inverse ? 2.0 * N + 1 : N + 1;  // grid points
-    // recurrence: coefficients in, point values out (forward) / g in, y out (inverse)
-    w.rec_bytes = 8.0 * (inverse ? gN + (N + 1) : (N + 1) + gN);
-    // Hahn blocks: coefficients and diagonals in (C_{n,m}, u_m, v_m), values out
-    w.asy_bytes = pt.nblk ? 8.0 * (gN + (N + 1)) + 8.0 * pt.M * (N + 1) + 16.0 * pt.M * gN : 0.0;
-    w.bnd_bytes = 8.0 * ((N + 1) + gN) + (inverse ? 8.0 * gN : 0.0);
-    return w;
-}
-
-cjt_status execute(bool inverse, const std::vector<Inst>& insts, hipStream_t st)
-{
-    if (insts.empty()) return CJT_OK;
     int dev = 0;
     CJT_HIP_TRY(hipGetDevice(&dev));
-    const bool fp32 = (insts[0].P->flags & CJT_FP32_BULK) != 0;
-    for (auto& x : insts) {
-        if (((x.P->flags & CJT_FP32_BULK) != 0) != fp32)
+    const bool fp32 = (plans[0]->flags & CJT_FP32_BULK) != 0;
+    for (const Plan* P : plans) {
+        if (((P->flags & CJT_FP32_BULK) != 0) != fp32)
             return fail(CJT_EINVAL, "all plans of a batch must share the precision flag");
-        if (x.P->device != dev) return fail(CJT_EINVAL, "plan belongs to another device");
-    }
-    // group by degree (one FFT length per launch), keeping the caller's order inside a group
-    std::vector<size_t> order(insts.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return insts[a].P->N < insts[b].P->N; });
-
-    std::lock_guard<std::mutex> lk(g_ws_mu);
-    Workspace& ws = g_ws[{dev, st}];
-
-    // chunks: runs of equal N whose FFT intermediates fit the limit
-    struct Chunk {
-        size_t first, count;
-        size_t tmp_bytes;
-    };
-    std::vector<Chunk> chunks;
-    size_t max_tmp = 0, persist = 0;
-    for (size_t i = 0; i < order.size();) {
-        const int64_t N = insts[order[i]].P->N;
-        Chunk c{i, 0, 0};
-        while (i < order.size() && insts[order[i]].P->N == N) {
-            Need nd = need_of(*insts[order[i]].P, inverse, fp32);
-            if (c.count > 0 && c.tmp_bytes + a256(nd.tmp) > ws_limit()) break;
-            c.tmp_bytes += a256(nd.tmp);
-            persist += a256(nd.p) + a256(nd.p2) + a256(nd.part);
-            ++c.count;
-            ++i;
-        }
-        max_tmp = std::max(max_tmp, c.tmp_bytes);
-        chunks.push_back(c);
-    }
-    cjt_status s = ws_reserve(ws, persist + max_tmp, insts.size(), st);
-    if (s != CJT_OK) return s;
-
-    // descriptors for every instance, in chunk order, copied once
-    {
-        char* base = (char*)ws.dev;
-        size_t poff = 0;                 // persistent region [0, persist)
-        for (const Chunk& c : chunks) {
-            size_t toff = persist;       // chunk region [persist, persist + max_tmp)
-            for (size_t q = 0; q < c.count; ++q) {
-                const size_t idx = c.first + q;
-                const Inst& x = insts[order[idx]];
-                const Plan& P = *x.P;
-                const Part& pt = inverse ? P.inv : P.fwd;
-                Need nd = need_of(P, inverse, fp32);
-                ExecDesc d{};
-                d.N = P.N;
-                d.G = inverse ? 2 * P.N : P.N;
-                d.alpha = P.alpha;
-                d.beta = P.beta;
-                d.M = pt.M;
-                d.nblk = pt.nblk;
-                for (int k = 0; k < pt.nblk; ++k) {
-                    d.deg_lo[k] = pt.deg_lo[k];
-                    d.deg_hi[k] = pt.deg_hi[k];
-                    d.win_lo[k] = pt.win_lo[k];
-                    d.win_hi[k] = pt.win_hi[k];
-                }
-                d.C = P.C;
-                d.uv = inverse ? P.uv_i : P.uv_f;
-                d.w = P.w;
-                d.s = P.s;
-                d.tasks = inverse ? P.d_tasks_i : P.d_tasks_f;
-                d.ntasks = (int32_t)(inverse ? P.tasks_i.size() : P.tasks_f.size());
-                d.rec0 = inverse ? P.i0 : P.f0;
-                d.recp = inverse ? P.ip : P.fp;
-                d.recm = inverse ? P.im : P.fm;
-                d.in = x.in;
-                d.out = x.out;
-                d.p = (double*)(base + poff);
-                poff += a256(nd.p);
-                d.p2 = nd.p2 ? (double*)(base + poff) : nullptr;
-                poff += a256(nd.p2);
-                d.part = nd.part ? (double*)(base + poff) : nullptr;
-                poff += a256(nd.part);
-                d.tmp = nd.tmp ? (void*)(base + toff) : nullptr;
-                toff += a256(nd.tmp);
-                ws.h_desc[idx] = d;
-            }
-        }
-    }
-    CJT_HIP_TRY(hipMemcpyAsync(ws.d_desc, ws.h_desc, sizeof(ExecDesc) * insts.size(), hipMemcpyHostToDevice, st));
-    CJT_HIP_TRY(hipEventRecord(ws.copied, st));
-    ws.pending = true;
-
-    // whole-call arguments for the recurrence kernels (any mix of N)
-    EngineArgs all{};
-    all.d_desc = ws.d_desc;
-    all.count = (int)insts.size();
-    all.stream = ws.aux;
-    int64_t maxN = 0;
-    Work wall;
-    for (const Inst& x : insts) {
-        const Plan& P = *x.P;
-        all.max_tasks = std::max(all.max_tasks, (int)(inverse ? P.tasks_i.size() : P.tasks_f.size()));
-        maxN = std::max(maxN, P.N);
-        Work w = work_of(P, inverse);
-        wall.rec_flops += w.rec_flops;
-        wall.rec_bytes += w.rec_bytes;
-    }
-    auto chunk_args = [&](const Chunk& c, Work* wk) {
-        EngineArgs ea{};
-        ea.d_desc = ws.d_desc + c.first;
-        ea.count = (int)c.count;
-        ea.stream = st;
-        for (size_t q = 0; q < c.count; ++q) {
-            const Plan& P = *insts[order[c.first + q]].P;
-            const Part& pt = inverse ? P.inv : P.fwd;
-            ea.max_jobs = std::max(ea.max_jobs, pt.nblk * pt.M);
-            if (pt.nblk > 0) ea.max_m = std::max(ea.max_m, pt.M);
-            Work x = work_of(P, inverse);
-            wk->asy_flops += x.asy_flops;
-            wk->bnd_flops += x.bnd_flops;
-            wk->asy_bytes += x.asy_bytes;
-            wk->bnd_bytes += x.bnd_bytes;
-        }
-        return ea;
-    };
-
-    if (!inverse) {
-        // recurrence part on the auxiliary stream, Hahn blocks on the caller's, then the final DCT-I
-        CJT_HIP_TRY(hipEventRecord(ws.fork, st));
-        CJT_HIP_TRY(hipStreamWaitEvent(ws.aux, ws.fork, 0));
-        {
-            ProfScope ps("rec_forward", wall.rec_flops, wall.rec_bytes, ws.aux);
-            if ((s = launch_rec_fwd(all)) != CJT_OK) return s;
-        }
-        CJT_HIP_TRY(hipEventRecord(ws.join, ws.aux));
-        for (const Chunk& c : chunks) {
-            Work wk;
-            EngineArgs ea = chunk_args(c, &wk);
-            const int64_t N = insts[order[c.first]].P->N;
-            if (ea.max_jobs > 0) {
-                if ((s = fft_geometry(N, fp32, st, &ea.geom)) != CJT_OK) return s;
-                label(ea, fp32 ? "hahn_fwd_cols_fp32" : "hahn_fwd_cols", fp32 ? "hahn_fwd_rows_fp32" : "hahn_fwd_rows",
-                      wk.asy_flops, wk.asy_bytes);
-                if ((s = launch_rdft(ea, Src::FwdAsy, Sink::FwdAsy, fp32)) != CJT_OK) return s;
-            }
-        }
-        CJT_HIP_TRY(hipStreamWaitEvent(st, ws.join, 0));
-        for (const Chunk& c : chunks) {
-            Work wk;
-            EngineArgs ea = chunk_args(c, &wk);
-            const int64_t N = insts[order[c.first]].P->N;
-            if ((s = fft_geometry(N, false, st, &ea.geom)) != CJT_OK) return s;
-            label(ea, "dct1_final_cols", "dct1_final_rows", wk.bnd_flops, wk.bnd_bytes);
-            if ((s = launch_rdft(ea, Src::FwdFinal, Sink::FwdFinal, false)) != CJT_OK) return s;
-        }
-    } else {
-        for (const Chunk& c : chunks) {
-            Work wk;
-            EngineArgs ea = chunk_args(c, &wk);
-            const int64_t N = insts[order[c.first]].P->N;
-            if ((s = fft_geometry(2 * N, false, st, &ea.geom)) != CJT_OK) return s;
-            label(ea, "dct1_initial_cols", "dct1_initial_rows", wk.bnd_flops, wk.bnd_bytes);
-            if ((s = launch_rdft(ea, Src::InvInit, Sink::InvInit, false)) != CJT_OK) return s;
-        }
-        CJT_HIP_TRY(hipEventRecord(ws.fork, st));
-        CJT_HIP_TRY(hipStreamWaitEvent(ws.aux, ws.fork, 0));
-        {
-            ProfScope ps("rec_inverse", wall.rec_flops, wall.rec_bytes, ws.aux);
-            if ((s = launch_rec_inv(all)) != CJT_OK) return s;
-        }
-        CJT_HIP_TRY(hipEventRecord(ws.join, ws.aux));
-        for (const Chunk& c : chunks) {
-            Work wk;
-            EngineArgs ea = chunk_args(c, &wk);
-            const int64_t N = insts[order[c.first]].P->N;
-            if (ea.max_jobs > 0) {
-                if ((s = fft_geometry(2 * N, fp32, st, &ea.geom)) != CJT_OK) return s;
-                label(ea, fp32 ? "hahn_inv_cols_fp32" : "hahn_inv_cols", fp32 ? "hahn_inv_rows_fp32" : "hahn_inv_rows",
-                      wk.asy_flops, wk.asy_bytes);
-                if ((s = launch_rdft(ea, Src::InvAsy, Sink::InvAsy, fp32)) != CJT_OK) return s;
-            } else {
-                dim3 grid((unsigned)((N + 1 + 255) / 256), (unsigned)c.count);
-                hipLaunchKernelGGL(k_zero_out, grid, dim3(256), 0, st, ea.d_desc);
-                CJT_HIP_TRY(hipGetLastError());
-            }
-        }
-        CJT_HIP_TRY(hipStreamWaitEvent(st, ws.join, 0));
-        all.stream = st;
-        ProfScope ps("rec_inverse_reduce", 0.0, 16.0 * (double)(maxN + 1) * all.count, st);
-        if ((s = launch_rec_inv_reduce(all, maxN)) != CJT_OK) return s;
+        if (P->device != dev) return fail(CJT_EINVAL, "plan belongs to another device");
     }
     return CJT_OK;
+}
+
+// One-shot execution: program built per call, descriptors and items uploaded
+// through the stream's pinned staging buffer, workspace kept per stream.
+cjt_status execute(bool inverse, const std::vector<const Plan*>& plans, const std::vector<int64_t>& io_off,
+                   const double* in, double* out, hipStream_t st)
+{
+    if (plans.empty()) return CJT_OK;
+    cjt_status s = check_batch(plans);
+    if (s != CJT_OK) return s;
+    int dev = 0;
+    CJT_HIP_TRY(hipGetDevice(&dev));
+    Built b;
+    if ((s = build_program(plans, io_off, inverse, ws_limit(), false, st, &b)) != CJT_OK) return s;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace& ws = g_ws[{dev, st}];
+    const size_t dbytes = a256(sizeof(ExecDesc) * b.pr.descs.size());
+    const size_t ibytes = sizeof(Item) * b.pr.items.size();
+    if ((s = ws_reserve(ws, std::max<size_t>(b.ws_bytes, 256), dbytes + ibytes, st)) != CJT_OK) return s;
+    bind_workspace(b, ws.dev);
+    for (ExecDesc& d : b.pr.descs) {
+        d.in = in + d.io_off;
+        d.out = out + d.io_off;
+    }
+    memcpy(ws.h_meta, b.pr.descs.data(), sizeof(ExecDesc) * b.pr.descs.size());
+    if (ibytes) memcpy(ws.h_meta + dbytes, b.pr.items.data(), ibytes);
+    CJT_HIP_TRY(hipMemcpyAsync(ws.d_meta, ws.h_meta, dbytes + ibytes, hipMemcpyHostToDevice, st));
+    CJT_HIP_TRY(hipEventRecord(ws.copied, st));
+    ws.pending = true;
+    return run_program(b.pr, (const ExecDesc*)ws.d_meta, (const Item*)(ws.d_meta + dbytes), st, ws.aux, ws.fork,
+                       ws.join, in, out);
 }
 
 void fill_part_info(const Part& p, cjt_partition_info* o)
@@ -617,8 +403,7 @@ static cjt_status single(bool inverse, cjt_plan_t plan, const double* d_in, doub
 {
     if (!plan || !d_in || !d_out) return fail(CJT_EINVAL, "null argument");
     if ((const void*)d_in == (const void*)d_out) return fail(CJT_EINVAL, "in-place transforms are not supported");
-    std::vector<Inst> v = {Inst{&plan->p, d_in, d_out}};
-    return execute(inverse, v, (hipStream_t)stream);
+    return execute(inverse, {&plan->p}, {0}, d_in, d_out, (hipStream_t)stream);
 }
 
 cjt_status cjt_forward(cjt_plan_t plan, const double* d_in, double* d_out, void* stream)
@@ -631,6 +416,21 @@ cjt_status cjt_inverse(cjt_plan_t plan, const double* d_in, double* d_out, void*
     return single(true, plan, d_in, d_out, stream);
 }
 
+static cjt_status gather(const cjt_plan_t* plans, int64_t count, const int64_t* offsets, std::vector<const Plan*>* v,
+                         std::vector<int64_t>* off)
+{
+    v->reserve((size_t)count);
+    off->reserve((size_t)count);
+    for (int64_t i = 0; i < count; ++i) {
+        if (!plans[i]) return fail(CJT_EINVAL, "null plan in batch");
+        if (offsets[i] < 0 || offsets[i + 1] - offsets[i] != plans[i]->p.N + 1)
+            return fail(CJT_EINVAL, "offsets do not match the plans' N + 1");
+        v->push_back(&plans[i]->p);
+        off->push_back(offsets[i]);
+    }
+    return CJT_OK;
+}
+
 static cjt_status batched(bool inverse, const cjt_plan_t* plans, int64_t count, const int64_t* offsets,
                           const double* d_in, double* d_out, void* stream)
 {
@@ -638,15 +438,11 @@ static cjt_status batched(bool inverse, const cjt_plan_t* plans, int64_t count, 
         return fail(CJT_EINVAL, "null argument");
     if (count == 0) return CJT_OK;
     if ((const void*)d_in == (const void*)d_out) return fail(CJT_EINVAL, "in-place transforms are not supported");
-    std::vector<Inst> v;
-    v.reserve((size_t)count);
-    for (int64_t i = 0; i < count; ++i) {
-        if (!plans[i]) return fail(CJT_EINVAL, "null plan in batch");
-        if (offsets[i] < 0 || offsets[i + 1] - offsets[i] != plans[i]->p.N + 1)
-            return fail(CJT_EINVAL, "offsets do not match the plans' N + 1");
-        v.push_back(Inst{&plans[i]->p, d_in + offsets[i], d_out + offsets[i]});
-    }
-    return execute(inverse, v, (hipStream_t)stream);
+    std::vector<const Plan*> v;
+    std::vector<int64_t> off;
+    cjt_status s = gather(plans, count, offsets, &v, &off);
+    if (s != CJT_OK) return s;
+    return execute(inverse, v, off, d_in, d_out, (hipStream_t)stream);
 }
 
 cjt_status cjt_forward_batched(const cjt_plan_t* plans, int64_t count, const int64_t* offsets, const double* d_in,
@@ -659,6 +455,99 @@ cjt_status cjt_inverse_batched(const cjt_plan_t* plans, int64_t count, const int
                                double* d_out, void* stream)
 {
     return batched(true, plans, count, offsets, d_in, d_out, stream);
+}
+
+static void batch_free(cjt_batch_s* b)
+{
+    if (b->ws) (void)hipFree(b->ws);
+    if (b->meta) (void)hipFree(b->meta);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
+    if (b->aux) (void)hipStreamDestroy(b->aux);
+    delete b;
+}
+
+cjt_status cjt_batch_create(cjt_batch_t* out, const cjt_plan_t* plans, int64_t count, const int64_t* offsets,
+                            unsigned flags, void* stream)
+{
+    if (!out) return fail(CJT_EINVAL, "null output");
+    *out = nullptr;
+    if (count <= 0 || !plans || !offsets) return fail(CJT_EINVAL, "empty batch or null argument");
+    if (flags != CJT_DIR_FWD && flags != CJT_DIR_INV) return fail(CJT_EINVAL, "flags must be CJT_DIR_FWD or CJT_DIR_INV");
+    std::vector<const Plan*> v;
+    std::vector<int64_t> off;
+    cjt_status s = gather(plans, count, offsets, &v, &off);
+    if (s != CJT_OK) return s;
+    if ((s = check_batch(v)) != CJT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    cjt_batch_s* b = new (std::nothrow) cjt_batch_s;
+    if (!b) return fail(CJT_ENOMEM, "host allocation failed");
+    b->inverse = flags == CJT_DIR_INV;
+    do {
+        if (hipGetDevice(&b->device) != hipSuccess) { s = fail(CJT_EDEVICE, "no HIP device"); break; }
+        // the whole batch's FFT intermediates at once: no chunking
+        if ((s = build_program(v, off, b->inverse, SIZE_MAX, true, st, &b->b)) != CJT_OK) break;
+        if (hipMalloc(&b->ws, std::max<size_t>(b->b.ws_bytes, 256)) != hipSuccess) {
+            s = fail(CJT_ENOMEM, "batch workspace allocation failed");
+            break;
+        }
+        bind_workspace(b->b, b->ws);
+        b->dbytes = a256(sizeof(ExecDesc) * b->b.pr.descs.size());
+        const size_t ibytes = sizeof(Item) * b->b.pr.items.size();
+        if (hipMalloc((void**)&b->meta, b->dbytes + ibytes + 1) != hipSuccess) {
+            s = fail(CJT_ENOMEM, "batch descriptor allocation failed");
+            break;
+        }
+        if (hipMemcpy(b->meta, b->b.pr.descs.data(), sizeof(ExecDesc) * b->b.pr.descs.size(), hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            (ibytes && hipMemcpy(b->meta + b->dbytes, b->b.pr.items.data(), ibytes, hipMemcpyHostToDevice) != hipSuccess)) {
+            s = fail(CJT_EDEVICE, "batch upload failed");
+            break;
+        }
+        if (hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess) {
+            s = fail(CJT_EDEVICE, "batch stream setup failed");
+            break;
+        }
+    } while (0);
+    if (s != CJT_OK) {
+        batch_free(b);
+        return s;
+    }
+    *out = b;
+    return CJT_OK;
+}
+
+cjt_status cjt_batch_execute(cjt_batch_t batch, const double* d_in, double* d_out, void* stream)
+{
+    if (!batch || !d_in || !d_out) return fail(CJT_EINVAL, "null argument");
+    if ((const void*)d_in == (const void*)d_out) return fail(CJT_EINVAL, "in-place transforms are not supported");
+    int dev = 0;
+    CJT_HIP_TRY(hipGetDevice(&dev));
+    if (dev != batch->device) return fail(CJT_EINVAL, "batch belongs to another device");
+    return run_program(batch->b.pr, (const ExecDesc*)batch->meta, (const Item*)(batch->meta + batch->dbytes),
+                       (hipStream_t)stream, batch->aux, batch->fork, batch->join, d_in, d_out);
+}
+
+cjt_status cjt_batch_query(cjt_batch_t batch, cjt_batch_info* out)
+{
+    if (!batch || !out) return fail(CJT_EINVAL, "null argument");
+    memset(out, 0, sizeof(*out));
+    out->count = (int64_t)batch->b.pr.descs.size();
+    out->launches = (int64_t)batch->b.pr.launches.size();
+    out->items = (int64_t)batch->b.pr.items.size();
+    out->workspace_bytes = batch->b.ws_bytes;
+    out->inverse = batch->inverse ? 1 : 0;
+    return CJT_OK;
+}
+
+cjt_status cjt_batch_destroy(cjt_batch_t batch)
+{
+    if (!batch) return CJT_OK;
+    CJT_HIP_TRY(hipDeviceSynchronize());
+    batch_free(batch);
+    return CJT_OK;
 }
 
 }  // extern "C"

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/cjt.h"
 
@@ -37,6 +38,25 @@ struct RecTask {
     int64_t off;
 };
 
+// Geometry of one complex FFT length L on the device.  Powers of two run
+// directly; any other L runs as a cyclic convolution of power-of-two length
+// P >= 2L-1 (Bluestein's chirp-z identity), with the same radix kernels.
+struct FftGeom {
+    int64_t L;        // complex length
+    int32_t logL;
+    int32_t single;   // 1: whole transform in one workgroup
+    int32_t L1, L2;   // two-pass split of the power-of-two length (L, or P for chirp-z)
+    int32_t logL1, logL2;
+    const void* tw;   // [2L'] e^{i pi q / L'}, L' = L (power of two) or P (chirp-z)
+    // chirp-z only
+    int32_t bluestein;
+    int32_t logP;
+    int64_t P;
+    const void* chirp;  // [L]   e^{i pi t^2 / L}
+    const void* bl;     // [P]   FFT_P of the kernel conj(chirp) wrapped cyclically
+    const void* utw;    // [L+1] e^{i pi s / L}, twiddles of the real-input untangling
+};
+
 // Everything one kernel needs to know about one transform of a launch.  Built
 // on the host for every call and copied to the device as an array.
 struct ExecDesc {
@@ -62,7 +82,17 @@ struct ExecDesc {
     double* p;                // forward: recurrence part of the point values (N+1); inverse: g = w .* f (2N+1)
     double* p2;               // forward: Hahn-block part of the point values (N+1)
     double* part;             // inverse: recurrence partial sums
-    void* tmp;                // FFT intermediates [nblk*M][L] complex
+    void* tmp;                // FFT intermediates, fft_job_bytes(L) per job
+    double* seg;              // recurrence segment records (long recurrences split in degree)
+    int64_t io_off;           // offset of this instance in the caller's input / output arrays
+    FftGeom geo;              // FFT of length L = G (FP64 tables)
+    FftGeom geob;             // the same length in the precision of the Hahn-block FFTs
+};
+
+// One work item of a launch: which descriptor it serves and up to three
+// kernel-specific indices (job, tile, task, segment, record slot, ...).
+struct Item {
+    int32_t desc, a, b, c;
 };
 
 // Read-only views in the constant address space: loads from wave-uniform
@@ -82,25 +112,6 @@ __device__ __forceinline__ d4 ld(cptr<d4> p) { return d4{p->x, p->y, p->z, p->w}
 
 // Wave-uniform copy of an int (the value must already be equal in all lanes).
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// Geometry of one complex FFT length L on the device.  Powers of two run
-// directly; any other L runs as a cyclic convolution of power-of-two length
-// P >= 2L-1 (Bluestein's chirp-z identity), with the same radix kernels.
-struct FftGeom {
-    int64_t L;        // complex length
-    int32_t logL;
-    int32_t single;   // 1: whole transform in one workgroup
-    int32_t L1, L2;   // two-pass split of the power-of-two length (L, or P for chirp-z)
-    int32_t logL1, logL2;
-    const void* tw;   // [2L'] e^{i pi q / L'}, L' = L (power of two) or P (chirp-z)
-    // chirp-z only
-    int32_t bluestein;
-    int32_t logP;
-    int64_t P;
-    const void* chirp;  // [L]   e^{i pi t^2 / L}
-    const void* bl;     // [P]   FFT_P of the kernel conj(chirp) wrapped cyclically
-    const void* utw;    // [L+1] e^{i pi s / L}, twiddles of the real-input untangling
-};
 
 constexpr int64_t kSingleMax = 4096;
 // Largest degree: the inverse's length-2N transform must fit the two-pass
@@ -133,28 +144,72 @@ struct ProfScope {
     hipStream_t st = nullptr;
 };
 
-// Launchers implemented in the .hip files.
-struct EngineArgs {
-    const ExecDesc* d_desc;   // device array of descriptors
-    int count;                // instances in the launch
-    int max_jobs;             // max nblk*M over the instances
-    int max_m;                // max M over the instances with blocks
-    int max_tasks;            // max ntasks over the instances
-    FftGeom geom;             // all instances of one launch share L
-    hipStream_t stream;
-    // timing labels and algorithmic work of the engine's launches (column pass, row pass)
-    const char* name1 = nullptr;
-    const char* name2 = nullptr;
-    double flops1 = 0, flops2 = 0, bytes1 = 0, bytes2 = 0;
-};
-
 enum class Src { FwdAsy, InvAsy, FwdFinal, InvInit, Moments };
 enum class Sink { FwdAsy, InvAsy, FwdFinal, InvInit, Weights };
 
-cjt_status launch_rdft(const EngineArgs& a, Src src, Sink sink, bool fp32);
-cjt_status launch_rec_fwd(const EngineArgs& a);
-cjt_status launch_rec_inv(const EngineArgs& a);
-cjt_status launch_rec_inv_reduce(const EngineArgs& a, int64_t maxN);
+// Kernels of the engine.  A transform call is a list of launches, each over a
+// flat list of work items that may mix instances of any degree.
+enum class Kind : int32_t {
+    Fork,            // the auxiliary stream waits for the caller's stream
+    Join,            // the caller's stream waits for the auxiliary stream
+    Patch,           // in/out pointers of every descriptor from the call's base pointers
+    FftSingle,       // whole power-of-two transform in one workgroup, all jobs of an instance
+    FftPass1,        // column pass of a two-pass transform, one (job, column tile)
+    FftPass2,        // row pass + untangling + sink, all jobs of an instance, one row tile
+    BsSingle,        // chirp-z transform in one workgroup
+    BsCol1, BsRow1,  // chirp-z, first transform (two passes)
+    BsCol2, BsRow2,  // chirp-z, second transform (two passes)
+    BsUntangle,      // chirp-z untangling + sink
+    RecFwd,          // forward recurrence over the whole degree range of a task
+    RecFwdSeg,       // forward recurrence over one degree segment of a long task (affine map)
+    RecFwdCombine,   // forward: chain the affine maps of a split task's segments
+    RecInvMaps,      // inverse: transfer maps of a split task's segments
+    RecInvInit,      // inverse: starting state of every segment of a split task
+    RecInv,          // inverse recurrence over a degree segment, reduced over points
+    RecInvReduce,    // inverse: sum of task partials, Hahn part, 1/A_n
+};
+
+struct Launch {
+    Kind kind;
+    int32_t stream = 0;        // 0: the caller's stream, 1: the auxiliary stream
+    Src src = Src::FwdAsy;
+    Sink sink = Sink::FwdAsy;
+    int32_t fp32 = 0;          // FFT arithmetic in FP32
+    int32_t nth = 0;           // threads per workgroup
+    int64_t item_off = 0;      // first item in the program's item array
+    int64_t nitems = 0;
+    size_t lds = 0;            // dynamic LDS bytes
+    size_t acc_off = 0;        // kernel-specific LDS offset
+    int32_t seg = 0;           // recurrence segment length (degrees)
+    const char* name = nullptr;
+    double flops = 0, bytes = 0;
+};
+
+struct Program {
+    std::vector<ExecDesc> descs;
+    std::vector<Item> items;
+    std::vector<Launch> launches;
+};
+
+// Appends the launches of one pass of the FFT engine over the instances
+// `which` (indices into pr.descs).  flops/bytes: algorithmic work per
+// instance, for the timing labels.
+cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sink, bool fp32, int stream,
+                   const char* name_cols, const char* name_rows, const std::vector<double>& flops,
+                   const std::vector<double>& bytes);
+// Recurrence launches over all instances; the segment length `seg` splits
+// tasks whose degree range exceeds 2*seg.  Returns the segment-record
+// doubles each instance needs (rec_seg_doubles) before the seg pointers are set.
+int32_t rec_segment_length(const Program& pr, const std::vector<const RecTask*>& tasks);
+int64_t rec_seg_doubles(const ExecDesc& d, const RecTask* tasks, int32_t seg);
+void add_rec_fwd(Program& pr, const std::vector<const RecTask*>& tasks, int32_t seg, int stream, double flops,
+                 double bytes);
+void add_rec_inv(Program& pr, const std::vector<const RecTask*>& tasks, int32_t seg, int stream, double flops,
+                 double bytes);
+void add_rec_inv_reduce(Program& pr, int stream, double bytes);
+
+cjt_status launch_fft(const Launch& L, const ExecDesc* d_desc, const Item* d_items, hipStream_t s);
+cjt_status launch_rec(const Launch& L, const ExecDesc* d_desc, const Item* d_items, hipStream_t s);
 cjt_status make_twiddles(int64_t L, bool fp32, const void** out, hipStream_t stream);
 cjt_status fft_twiddles_cached(int64_t L, bool fp32, hipStream_t st, const void** out);
 cjt_status make_chirp_tables(FftGeom* g, bool fp32, hipStream_t st);

@@ -444,41 +444,34 @@ cjt_status build_plan_device(Plan* P, hipStream_t st)
     d.beta = b;
     d.in = mu;
     d.out = P->w;
-    ExecDesc* dd = nullptr;
-    CJT_HIP_TRY(hipMalloc(&dd, sizeof(ExecDesc)));
-    cjt_status stt = CJT_OK;
+    cjt_status stt = fft_geometry(2 * N, false, st, &d.geo);
+    if (stt != CJT_OK) return stt;
+    d.geob = d.geo;
+    const size_t tmp_bytes = fft_job_bytes(2 * N, false);
+    const size_t dbytes = (sizeof(ExecDesc) + 255) & ~(size_t)255;
+    char* buf = nullptr;  // [descriptor | items | FFT intermediates]
+    Program pr;
+    pr.descs.push_back(d);
+    std::vector<double> fl(1, 0.0), by(1, 0.0);
+    stt = add_fft(pr, std::vector<int>{0}, Src::Moments, Sink::Weights, false, 0, nullptr, nullptr, fl, by);
+    if (stt != CJT_OK) return stt;
+    const size_t ibytes = (sizeof(Item) * pr.items.size() + 255) & ~(size_t)255;
+    CJT_HIP_TRY(hipMalloc(&buf, dbytes + ibytes + tmp_bytes));
+    pr.descs[0].tmp = tmp_bytes ? (void*)(buf + dbytes + ibytes) : nullptr;
     do {
-        if (hipMemcpyAsync(dd, &d, sizeof(ExecDesc), hipMemcpyHostToDevice, st) != hipSuccess) {
+        if (hipMemcpyAsync(buf, pr.descs.data(), sizeof(ExecDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(buf + dbytes, pr.items.data(), sizeof(Item) * pr.items.size(), hipMemcpyHostToDevice,
+                           st) != hipSuccess) {
             stt = fail(CJT_EDEVICE, "descriptor copy failed");
             break;
         }
-        EngineArgs ea{};
-        ea.d_desc = dd;
-        ea.count = 1;
-        ea.max_jobs = 1;
-        ea.max_m = 1;
-        stt = fft_geometry(2 * N, false, st, &ea.geom);
-        if (stt != CJT_OK) break;
-        ea.stream = st;
-        // two-pass transforms need an intermediate buffer
-        void* tmp = nullptr;
-        const size_t tmp_bytes = fft_job_bytes(2 * N, false);
-        if (tmp_bytes > 0) {
-            if (hipMalloc(&tmp, tmp_bytes) != hipSuccess) {
-                stt = fail(CJT_ENOMEM, "weights workspace");
-                break;
-            }
-            d.tmp = tmp;
-            if (hipMemcpyAsync(dd, &d, sizeof(ExecDesc), hipMemcpyHostToDevice, st) != hipSuccess) {
-                stt = fail(CJT_EDEVICE, "descriptor copy failed");
-                break;
-            }
+        for (const Launch& L : pr.launches) {
+            stt = launch_fft(L, (const ExecDesc*)buf, (const Item*)(buf + dbytes) + L.item_off, st);
+            if (stt != CJT_OK) break;
         }
-        stt = launch_rdft(ea, Src::Moments, Sink::Weights, false);
         if (hipStreamSynchronize(st) != hipSuccess && stt == CJT_OK) stt = fail(CJT_EDEVICE, "plan build failed");
-        if (tmp) (void)hipFree(tmp);
     } while (0);
-    (void)hipFree(dd);
+    (void)hipFree(buf);
     if (stt != CJT_OK) return stt;
     CJT_HIP_TRY(hipStreamSynchronize(st));
     return CJT_OK;

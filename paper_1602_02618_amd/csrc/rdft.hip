@@ -25,9 +25,16 @@
 // stride L2, times exp(2 pi i n2 k1 / L)) writes intermediates to global memory,
 // and a row pass (L2-point FFTs) pairs rows k1 and L1-k1 so each workgroup has
 // both Z_s and Z_{L-s} for the untangling.  The row pass loops over all Hahn
-// terms (m) and blocks (k) of its rows and accumulates in registers, so each
-// output is written once.
+// terms (m) and blocks (k) of its rows and accumulates in LDS, so each output
+// is written once.  Lengths that are not powers of two go through the chirp-z
+// identity with the same power-of-two passes.
+//
+// Every kernel works on a flat list of work items (descriptor, job, tile), so
+// one launch serves any mix of degrees; the geometry of each instance's
+// length is read from its descriptor.
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "cjt_internal.h"
 #include "fft_lds.h"
@@ -42,6 +49,7 @@ struct Source;
 template <>
 struct Source<Src::FwdAsy> {
     // job = k * M + m
+    static constexpr bool kMulti = true;
     __device__ static bool valid(const ExecDesc& d, int job) { return job < d.nblk * d.M; }
     __device__ static cx<double> load(const ExecDesc& d, int job, int64_t t)
     {
@@ -57,6 +65,7 @@ struct Source<Src::FwdAsy> {
 
 template <>
 struct Source<Src::InvAsy> {
+    static constexpr bool kMulti = true;
     __device__ static bool valid(const ExecDesc& d, int job) { return job < d.nblk * d.M; }
     // a_j = u_m(theta_j) g_j, b_j = v_m(theta_j) g_j on the window (zero elsewhere);
     // r_0 = a_0, r_G = a_G, r_j = (a_j + b_j)/2 and r_{2G-j} = (a_j - b_j)/2 for 0 < j < G.
@@ -83,6 +92,7 @@ struct Source<Src::InvAsy> {
 
 template <>
 struct Source<Src::FwdFinal> {
+    static constexpr bool kMulti = false;
     __device__ static bool valid(const ExecDesc&, int job) { return job == 0; }
     // p = recurrence part + Hahn-block part (the latter only if the plan has blocks)
     __device__ static double pv(const ExecDesc& d, int64_t j) { return d.nblk > 0 ? d.p[j] + d.p2[j] : d.p[j]; }
@@ -97,6 +107,7 @@ struct Source<Src::FwdFinal> {
 
 template <>
 struct Source<Src::InvInit> {
+    static constexpr bool kMulti = false;
     __device__ static bool valid(const ExecDesc&, int job) { return job == 0; }
     __device__ static cx<double> load(const ExecDesc& d, int, int64_t t)
     {
@@ -107,6 +118,7 @@ struct Source<Src::InvInit> {
 
 template <>
 struct Source<Src::Moments> {
+    static constexpr bool kMulti = false;
     // in = mu_0..mu_G, halved at both ends
     __device__ static bool valid(const ExecDesc&, int job) { return job == 0; }
     __device__ static cx<double> load(const ExecDesc& d, int, int64_t t)
@@ -207,30 +219,108 @@ __device__ __forceinline__ void untangle(cx<T> za, cx<T> zb, cx<T> w, cx<double>
     xls = {(double)(e.re - wo.re), -(double)(e.im - wo.im)};
 }
 
-// ------------------------------------------------------------------ single pass
+// ------------------------------------------------------------------ helpers
 
 template <typename T>
 __device__ __forceinline__ cx<T> to_t(cx<double> v) { return {(T)v.re, (T)v.im}; }
 
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+
+// Geometry of an instance's length in the arithmetic precision T.
+template <typename T>
+__device__ __forceinline__ const FftGeom& geom_of(const ExecDesc& d);
+template <>
+__device__ __forceinline__ const FftGeom& geom_of<double>(const ExecDesc& d) { return d.geo; }
+template <>
+__device__ __forceinline__ const FftGeom& geom_of<float>(const ExecDesc& d) { return d.geob; }
+
+// X_s and X_{L-s} of the real-input DFT from the complex FFT Z (any L; s <= L/2).
+template <typename T, typename ZAt>
+__device__ __forceinline__ void untangle_at(ZAt Z, int64_t L, int64_t s, cx<T> w, cx<double>& xa, cx<double>& xb)
+{
+    if (s == 0) {
+        const cx<T> z = Z(0);
+        xa = {(double)z.re + (double)z.im, 0.0};
+        xb = {(double)z.re - (double)z.im, 0.0};
+    } else if (2 * s == L) {
+        const cx<T> z = Z(s);
+        xa = {(double)z.re, (double)z.im};
+        xb = xa;
+    } else {
+        untangle<T>(Z(s), Z(L - s), w, xa, xb);
+    }
+}
+
+// Column pass of a power-of-two FFT of length F = F1 F2 (F1 = 2^lg1 <= 2048,
+// F2 = 2^lg2): TC = 2048 / F1 columns per workgroup of 128 threads; thread lt
+// of column c holds n1 = lt + r F1/16.  Output k1 of column n2 is multiplied by
+// e^{2 pi i n2 k1 / F}.  load(t) gives input t = n1 F2 + n2; store(k1 F2 + n2, v).
+template <typename T, typename LoadF, typename StoreF>
+__device__ __forceinline__ void col_pass(cx<T>* lds, int lg1, int lg2, const cx<T>* __restrict__ tw, int64_t tile,
+                                         LoadF load, StoreF store)
+{
+    const int F1 = 1 << lg1;
+    const int64_t F2 = (int64_t)1 << lg2, F = F2 << lg1;
+    const int TC = F1 >= 2048 ? 1 : 2048 / F1;
+    const int tid = threadIdx.x;
+    const int c = tid % TC, lt = tid / TC;
+    const int64_t col = tile * TC + c;
+    const int step = F1 >> 4;
+    cx<T> v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = load((int64_t)(lt + r * step) * F2 + col);
+    fft_reg<T>(v, lds + c * slice_stride(F1), lg1, lt, true, tw, 2 * F);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int64_t k1 = fft_out_index(s, lt, lg1);
+        const int64_t q = (2 * col * k1) & (2 * F - 1);  // e^{2 pi i n2 k1 / F} = tw[2 n2 k1 mod 2F]
+        store(k1 * F2 + col, cmul(v[s], tw[q]));
+    }
+}
+
+// Row pass: TR = max(1, 2048 / F2) rows k1 per workgroup (F2/16 threads each);
+// load(k1 F2 + n2), store(k1 + F1 k2, X) in natural frequency order.
+template <typename T, typename LoadF, typename StoreF>
+__device__ __forceinline__ void row_pass(cx<T>* lds, int lg1, int lg2, const cx<T>* __restrict__ tw, int64_t tile,
+                                         LoadF load, StoreF store)
+{
+    const int64_t F1 = (int64_t)1 << lg1;
+    const int F2 = 1 << lg2;
+    const int64_t F = F1 << lg2;
+    const int TR = F2 >= 2048 ? 1 : 2048 / F2;
+    const int tpr = F2 >> 4;
+    const int tid = threadIdx.x;
+    const int rr = tid / tpr, lt = tid - rr * tpr;
+    const int64_t k1 = tile * TR + rr;
+    cx<T> v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = load(k1 * F2 + lt + r * tpr);
+    fft_reg<T>(v, lds + rr * slice_stride(F2), lg2, lt, true, tw, 2 * F);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) store(k1 + F1 * fft_out_index(s, lt, lg2), v[s]);
+}
+
+// ------------------------------------------------------------------ power of two, one workgroup
+
 // One workgroup per instance; the whole length-L transform lives in LDS.
-// Loops over all jobs of the instance and accumulates per thread.
+// Loops over all jobs of the instance and accumulates per thread in LDS.
 template <typename T, Src S, Sink K>
-__global__ void __launch_bounds__(256) k_single(const ExecDesc* __restrict__ descs, FftGeom g, int max_jobs,
+__global__ void __launch_bounds__(256) k_single(const ExecDesc* __restrict__ descs, const Item* __restrict__ items,
                                                 size_t acc_off)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    const ExecDesc& d = descs[blockIdx.x];
+    const ExecDesc& d = descs[items[blockIdx.x].desc];
+    const FftGeom& g = geom_of<T>(d);
     const int L = (int)g.L;
     const int tid = threadIdx.x, nth = blockDim.x;
     const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
     const int nel = L / 2 + 1;  // elements s = 0..L/2
-    // per-thread accumulators in LDS: acc[slot * nth + tid]
     double* acc = reinterpret_cast<double*>(smem_raw + acc_off);
     for (int i = 0; i < kSlots; ++i) acc[i * nth + tid] = 0.0;
-
-    for (int job = 0; job < max_jobs; ++job) {
-        if (!Source<S>::valid(d, job)) break;
+    const int njobs = Source<S>::kMulti ? d.nblk * d.M : 1;
+    for (int job = 0; job < njobs; ++job) {
         for (int t = tid; t < L; t += nth) buf[lds_pad(t)] = to_t<T>(Source<S>::load(d, job, t));
         __syncthreads();
         lds_fft<T>(buf, g.logL, 1, tw, 2 * g.L);
@@ -239,17 +329,7 @@ __global__ void __launch_bounds__(256) k_single(const ExecDesc* __restrict__ des
             const int s = tid + q * nth;
             if (s >= nel) break;
             cx<double> xa, xb;
-            if (s == 0) {
-                cx<T> z = buf[lds_pad(0)];
-                xa = {(double)z.re + (double)z.im, 0.0};
-                xb = {(double)z.re - (double)z.im, 0.0};
-            } else if (2 * s == L) {
-                cx<T> z = buf[lds_pad(s)];
-                xa = {(double)z.re, (double)z.im};
-                xb = xa;
-            } else {
-                untangle<T>(buf[lds_pad(s)], buf[lds_pad(L - s)], tw[s], xa, xb);
-            }
+            untangle_at<T>([&](int64_t i) { return buf[lds_pad((int)i)]; }, L, s, tw[s], xa, xb);
             acc[(2 * q) * nth + tid] += Target<K>::contrib(d, job, s, xa);
             if (2 * s != L) acc[(2 * q + 1) * nth + tid] += Target<K>::contrib(d, job, L - s, xb);
         }
@@ -264,78 +344,65 @@ __global__ void __launch_bounds__(256) k_single(const ExecDesc* __restrict__ des
     }
 }
 
-// ------------------------------------------------------------------ two passes
+// ------------------------------------------------------------------ power of two, two passes
 
-// Column pass: TC consecutive columns n2 per workgroup, L1-point FFTs over n1
-// held in registers (thread lt of a column owns n1 = lt + r L1/16), multiplied
-// by exp(2 pi i n2 k1 / L) and written to tmp[job][k1 L2 + n2].
+// Column pass, item (desc, job, column tile): writes tmp[job][k1 L2 + n2].
 template <typename T, Src S>
-__global__ void __launch_bounds__(256) k_pass1(const ExecDesc* __restrict__ descs, FftGeom g, int TC)
+__global__ void __launch_bounds__(128) k_pass1(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-    const ExecDesc& d = descs[blockIdx.z];
-    const int job = blockIdx.y;
-    if (!Source<S>::valid(d, job)) return;
-    const int L1 = g.L1, L2 = g.L2;
-    const int64_t L = g.L;
-    const int tid = threadIdx.x;
-    const int c = tid % TC, lt = tid / TC;
-    const int64_t col = (int64_t)blockIdx.x * TC + c;
-    const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
-    const int step = L1 >> 4;
-    cx<T> v[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = to_t<T>(Source<S>::load(d, job, (int64_t)(lt + r * step) * L2 + col));
-    fft_reg<T>(v, lds + c * slice_stride(L1), g.logL1, lt, true, tw, 2 * L);
-    cx<T>* out = reinterpret_cast<cx<T>*>(d.tmp) + (int64_t)job * L;
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-        const int64_t k1 = fft_out_index(s, lt, g.logL1);
-        const int64_t q = (2 * col * k1) & (2 * L - 1);  // exp(2 pi i n2 k1 / L) = tw[2 n2 k1 mod 2L]
-        out[k1 * L2 + col] = cmul(v[s], tw[q]);
-    }
+    const Item it = items[blockIdx.x];
+    const ExecDesc& d = descs[it.desc];
+    const FftGeom& g = geom_of<T>(d);
+    const int job = it.a;
+    cx<T>* out = reinterpret_cast<cx<T>*>(d.tmp) + (int64_t)job * g.L;
+    col_pass<T>(
+        lds, g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw), it.b,
+        [&](int64_t t) { return to_t<T>(Source<S>::load(d, job, t)); }, [&](int64_t i, cx<T> v) { out[i] = v; });
 }
 
-// Row pass: TU units per workgroup; unit u holds rows u and L1-u (unit 0 holds
-// rows 0 and L1/2).  Element (u, k2) pairs Z at row u, position k2 with Z at
-// row L1-u, position L2-1-k2, which are Z_s and Z_{L-s} for s = u + L1 k2.
-// The L2-point FFTs run in registers; their outputs go through LDS once so
-// that each thread can fetch both members of its pairs.
-template <typename T, Sink K>
-__global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ descs, FftGeom g, int TU, int max_jobs,
-                                               int src_single_job, size_t acc_off)
+// Row pass, item (desc, unit tile): TU units per workgroup; unit u holds rows
+// u and L1-u (unit 0 holds rows 0 and L1/2).  Element (u, k2) pairs Z at row
+// u, position k2 with Z at row L1-u, position L2-1-k2, which are Z_s and
+// Z_{L-s} for s = u + L1 k2.  The L2-point FFTs run in registers; their
+// outputs go through LDS once so each thread can fetch both members of its pairs.
+template <typename T, Sink K, bool kMulti>
+__global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ descs, const Item* __restrict__ items,
+                                               size_t acc_off)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    const ExecDesc& d = descs[blockIdx.z];
+    const Item it = items[blockIdx.x];
+    const ExecDesc& d = descs[it.desc];
+    const FftGeom& g = geom_of<T>(d);
     const int L1 = g.L1, L2 = g.L2;
     const int64_t L = g.L;
-    const int unit0 = blockIdx.x * TU;
+    const int TU = L2 >= 1024 ? 1 : 1024 / L2;
+    const int unit0 = it.b * TU;
     const int tid = threadIdx.x, nth = blockDim.x;
     const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
-    const int tpr = L2 >> 4;               // threads per row
+    const int tpr = L2 >> 4;  // threads per row
     const int rs = tid / tpr, lt = tid - rs * tpr;
     const int my_unit = unit0 + (rs >> 1);
     const int my_row = (rs & 1) == 0 ? my_unit : (my_unit == 0 ? L1 / 2 : L1 - my_unit);
-    // TU * L2 regular elements per workgroup, kEPT = 8 per thread (nth = TU L2 / 8)
-    constexpr int ept = kEPT;
+    constexpr int ept = kEPT;  // TU * L2 regular elements per workgroup, kEPT per thread
     const bool has_half = (unit0 == 0) && (tid == nth - 1);  // thread that also owns s = L/2
+    const int sst = slice_stride(L2);
 
-    // per-thread accumulators in LDS: acc[slot * nth + tid], slots 0..2*ept (2*ept = s = L/2)
     double* acc = reinterpret_cast<double*>(smem_raw + acc_off);
     for (int i = 0; i <= 2 * ept; ++i) acc[i * nth + tid] = 0.0;
 
     // jobs in the order (m, k), k fastest, so that the diagonals of term m are
     // re-read from L2 for every block
-    const int njobs = src_single_job ? 1 : d.nblk * d.M;
-    for (int it = 0; it < njobs; ++it) {
-        const int job = src_single_job ? 0 : (it % d.nblk) * d.M + it / d.nblk;
+    const int njobs = kMulti ? d.nblk * d.M : 1;
+    for (int iter = 0; iter < njobs; ++iter) {
+        const int job = kMulti ? (iter % d.nblk) * d.M + iter / d.nblk : 0;
         const cx<T>* in = reinterpret_cast<const cx<T>*>(d.tmp) + (int64_t)job * L + (int64_t)my_row * L2;
         cx<T> v[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = in[lt + r * tpr];
-        cx<T>* slice = buf + rs * slice_stride(L2);
+        cx<T>* slice = buf + rs * sst;
         fft_reg<T>(v, slice, g.logL2, lt, true, tw, 2 * L);
 #pragma unroll
         for (int s = 0; s < 16; ++s) slice[lds_pad(fft_out_index(s, lt, g.logL2))] = v[s];
@@ -351,20 +418,20 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
             if (unit == 0) {
                 if (k2 < L2 / 2) {
                     s = L1 / 2 + (int64_t)L1 * k2;
-                    untangle<T>(buf[rb * slice_stride(L2) + lds_pad(k2)], buf[rb * slice_stride(L2) + lds_pad(L2 - 1 - k2)], tw[s], xa, xb);
+                    untangle<T>(buf[rb * sst + lds_pad(k2)], buf[rb * sst + lds_pad(L2 - 1 - k2)], tw[s], xa, xb);
                 } else if (k2 == L2 / 2) {
                     s = 0;
-                    cx<T> z = buf[ra * slice_stride(L2)];
+                    cx<T> z = buf[ra * sst];
                     xa = {(double)z.re + (double)z.im, 0.0};
                     xb = {(double)z.re - (double)z.im, 0.0};
                 } else {
                     const int kk = k2 - L2 / 2;
                     s = (int64_t)L1 * kk;
-                    untangle<T>(buf[ra * slice_stride(L2) + lds_pad(kk)], buf[ra * slice_stride(L2) + lds_pad(L2 - kk)], tw[s], xa, xb);
+                    untangle<T>(buf[ra * sst + lds_pad(kk)], buf[ra * sst + lds_pad(L2 - kk)], tw[s], xa, xb);
                 }
             } else {
                 s = unit + (int64_t)L1 * k2;
-                untangle<T>(buf[ra * slice_stride(L2) + lds_pad(k2)], buf[rb * slice_stride(L2) + lds_pad(L2 - 1 - k2)], tw[s], xa, xb);
+                untangle<T>(buf[ra * sst + lds_pad(k2)], buf[rb * sst + lds_pad(L2 - 1 - k2)], tw[s], xa, xb);
             }
             acc[(2 * q) * nth + tid] += Target<K>::contrib(d, job, s, xa);
             acc[(2 * q + 1) * nth + tid] += Target<K>::contrib(d, job, L - s, xb);
@@ -403,119 +470,106 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
 // F(b~) is a per-length table.  Per job: two P-point transforms (column + row
 // passes each), then the untangling of the length-2L real DFT from Z.
 //
-// Job storage (complex, per job): [0, P) column-pass output, [P, 2P) first
-// transform in natural order, [2P, 2P+L) Z.
+// Job storage (complex, 2P per job): [0, P) column-pass output; [P, 2P) the
+// first transform in natural order, then Z in [P, P+L) after the second.
 
 template <typename T>
-__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
-
-// stage 0: kernel spectrum (input b~ from the chirp table, output to bl)
-// stage 1: input a_t = source(t) c_t, output A (natural order)
-// stage 2: input conj(A_t F(b~)_t), output Z_s = c_s conj(E_s)/P for s < L
-template <typename T, Src S, int STAGE>
-__global__ void __launch_bounds__(256) k_bs_col(const ExecDesc* __restrict__ descs, FftGeom g, int TC, cx<T>* scratch)
+__device__ __forceinline__ cx<T>* bs_job(const ExecDesc& d, const FftGeom& g, int job)
 {
-    extern __shared__ unsigned char smem_raw[];
-    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-    const int64_t P = g.P, L = g.L;
-    const int P1 = g.L1, P2 = g.L2;
-    const int job = blockIdx.y;
-    const ExecDesc* d = STAGE == 0 ? nullptr : &descs[blockIdx.z];
-    if constexpr (STAGE != 0)
-        if (!Source<S>::valid(*d, job)) return;
-    const int tid = threadIdx.x;
-    const int c = tid % TC, lt = tid / TC;
-    const int64_t col = (int64_t)blockIdx.x * TC + c;
-    const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
-    const cx<T>* chirp = reinterpret_cast<const cx<T>*>(g.chirp);
-    const cx<T>* bl = reinterpret_cast<const cx<T>*>(g.bl);
-    cx<T>* base = STAGE == 0 ? scratch : reinterpret_cast<cx<T>*>(d->tmp) + (int64_t)job * (2 * P + L);
-    const int step = P1 >> 4;
-    cx<T> v[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int64_t t = (int64_t)(lt + r * step) * P2 + col;
-        cx<T> x = {(T)0, (T)0};
-        if constexpr (STAGE == 0) {
-            if (t < L) x = conj(chirp[t]);
-            else if (t > P - L) x = conj(chirp[P - t]);
-        } else if constexpr (STAGE == 1) {
-            if (t < L) x = cmul(to_t<T>(Source<S>::load(*d, job, t)), chirp[t]);
-        } else {
-            x = conj(cmul(base[P + t], bl[t]));
-        }
-        v[r] = x;
-    }
-    fft_reg<T>(v, lds + c * slice_stride(P1), g.logL1, lt, true, tw, 2 * P);
-#pragma unroll
-    for (int s2 = 0; s2 < 16; ++s2) {
-        const int64_t k1 = fft_out_index(s2, lt, g.logL1);
-        const int64_t q = (2 * col * k1) & (2 * P - 1);
-        base[k1 * P2 + col] = cmul(v[s2], tw[q]);
-    }
+    return reinterpret_cast<cx<T>*>(d.tmp) + (int64_t)job * 2 * g.P;
 }
 
-template <typename T, Src S, int STAGE>
-__global__ void __launch_bounds__(256) k_bs_row(const ExecDesc* __restrict__ descs, FftGeom g, int TR, cx<T>* scratch,
-                                                cx<T>* bl_out)
+// first transform, column pass: input a_t = source(t) c_t (zero for t >= L)
+template <typename T, Src S>
+__global__ void __launch_bounds__(128) k_bs_col1(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
 {
     extern __shared__ unsigned char smem_raw[];
-    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-    const int64_t P = g.P, L = g.L;
-    const int P1 = g.L1, P2 = g.L2;
-    const int job = blockIdx.y;
-    const ExecDesc* d = STAGE == 0 ? nullptr : &descs[blockIdx.z];
-    if constexpr (STAGE != 0)
-        if (!Source<S>::valid(*d, job)) return;
-    const int tid = threadIdx.x;
-    const int tpr = P2 >> 4;
-    const int rr = tid / tpr, lt = tid - rr * tpr;
-    const int64_t k1 = (int64_t)blockIdx.x * TR + rr;
-    const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
+    const Item it = items[blockIdx.x];
+    const ExecDesc& d = descs[it.desc];
+    const FftGeom& g = geom_of<T>(d);
+    const int job = it.a;
+    const int64_t L = g.L;
     const cx<T>* chirp = reinterpret_cast<const cx<T>*>(g.chirp);
-    cx<T>* base = STAGE == 0 ? scratch : reinterpret_cast<cx<T>*>(d->tmp) + (int64_t)job * (2 * P + L);
-    cx<T> v[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = base[k1 * P2 + lt + r * tpr];
-    fft_reg<T>(v, lds + rr * slice_stride(P2), g.logL2, lt, true, tw, 2 * P);
+    cx<T>* base = bs_job<T>(d, g, job);
+    col_pass<T>(
+        reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw), it.b,
+        [&](int64_t t) {
+            return t < L ? cmul(to_t<T>(Source<S>::load(d, job, t)), chirp[t]) : cx<T>{(T)0, (T)0};
+        },
+        [&](int64_t i, cx<T> v) { base[i] = v; });
+}
+
+// first transform, row pass: A in natural order to [P, 2P)
+template <typename T>
+__global__ void __launch_bounds__(256) k_bs_row1(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const Item it = items[blockIdx.x];
+    const ExecDesc& d = descs[it.desc];
+    const FftGeom& g = geom_of<T>(d);
+    cx<T>* base = bs_job<T>(d, g, it.a);
+    const int64_t P = g.P;
+    row_pass<T>(
+        reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw), it.b,
+        [&](int64_t i) { return base[i]; }, [&](int64_t i, cx<T> v) { base[P + i] = v; });
+}
+
+// second transform, column pass: input conj(A_t F(b~)_t)
+template <typename T>
+__global__ void __launch_bounds__(128) k_bs_col2(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const Item it = items[blockIdx.x];
+    const ExecDesc& d = descs[it.desc];
+    const FftGeom& g = geom_of<T>(d);
+    cx<T>* base = bs_job<T>(d, g, it.a);
+    const int64_t P = g.P;
+    const cx<T>* bl = reinterpret_cast<const cx<T>*>(g.bl);
+    col_pass<T>(
+        reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw), it.b,
+        [&](int64_t t) { return conj(cmul(base[P + t], bl[t])); }, [&](int64_t i, cx<T> v) { base[i] = v; });
+}
+
+// second transform, row pass: Z_s = c_s conj(E_s) / P for s < L, to [P, P+L)
+template <typename T>
+__global__ void __launch_bounds__(256) k_bs_row2(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const Item it = items[blockIdx.x];
+    const ExecDesc& d = descs[it.desc];
+    const FftGeom& g = geom_of<T>(d);
+    cx<T>* base = bs_job<T>(d, g, it.a);
+    const int64_t P = g.P, L = g.L;
+    const cx<T>* chirp = reinterpret_cast<const cx<T>*>(g.chirp);
     const T invP = (T)1 / (T)P;
-#pragma unroll
-    for (int s2 = 0; s2 < 16; ++s2) {
-        const int64_t k2 = fft_out_index(s2, lt, g.logL2);
-        const int64_t sidx = k1 + (int64_t)P1 * k2;
-        if constexpr (STAGE == 0) bl_out[sidx] = v[s2];
-        else if constexpr (STAGE == 1) base[P + sidx] = v[s2];
-        else if (sidx < L) base[2 * P + sidx] = cmul(chirp[sidx], cscale(conj(v[s2]), invP));
-    }
+    row_pass<T>(
+        reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw), it.b,
+        [&](int64_t i) { return base[i]; },
+        [&](int64_t s, cx<T> v) {
+            if (s < L) base[P + s] = cmul(chirp[s], cscale(conj(v), invP));
+        });
 }
 
 // Untangling of the length-2L real DFT from Z, summed over the jobs of the
-// instance (terms m outer, blocks k inner); one element (s, L-s) per thread.
-template <typename T, Sink K>
-__global__ void __launch_bounds__(256) k_bs_untangle(const ExecDesc* __restrict__ descs, FftGeom g, int single_job)
+// instance (terms m outer, blocks k inner); item (desc, tile of 256 elements
+// (s, L-s)).
+template <typename T, Sink K, bool kMulti>
+__global__ void __launch_bounds__(256) k_bs_untangle(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
 {
-    const ExecDesc& d = descs[blockIdx.y];
+    const Item it = items[blockIdx.x];
+    const ExecDesc& d = descs[it.desc];
+    const FftGeom& g = geom_of<T>(d);
     const int64_t L = g.L, P = g.P;
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t s = (int64_t)it.b * blockDim.x + threadIdx.x;
     if (s > L / 2) return;
     const cx<T>* utw = reinterpret_cast<const cx<T>*>(g.utw);
-    const int njobs = single_job ? 1 : d.nblk * d.M;
+    const int njobs = kMulti ? d.nblk * d.M : 1;
     double a0 = 0.0, a1 = 0.0;
-    for (int it = 0; it < njobs; ++it) {
-        const int job = single_job ? 0 : (it % d.nblk) * d.M + it / d.nblk;
-        const cx<T>* Z = reinterpret_cast<const cx<T>*>(d.tmp) + (int64_t)job * (2 * P + L) + 2 * P;
+    for (int iter = 0; iter < njobs; ++iter) {
+        const int job = kMulti ? (iter % d.nblk) * d.M + iter / d.nblk : 0;
+        const cx<T>* Z = reinterpret_cast<const cx<T>*>(d.tmp) + (int64_t)job * 2 * P + P;
         cx<double> xa, xb;
-        if (s == 0) {
-            const cx<T> z = Z[0];
-            xa = {(double)z.re + (double)z.im, 0.0};
-            xb = {(double)z.re - (double)z.im, 0.0};
-        } else if (2 * s == L) {
-            const cx<T> z = Z[s];
-            xa = {(double)z.re, (double)z.im};
-            xb = xa;
-        } else {
-            untangle<T>(Z[s], Z[L - s], utw[s], xa, xb);
-        }
+        untangle_at<T>([&](int64_t i) { return Z[i]; }, L, s, utw[s], xa, xb);
         a0 += Target<K>::contrib(d, job, s, xa);
         if (2 * s != L) a1 += Target<K>::contrib(d, job, L - s, xb);
     }
@@ -525,12 +579,13 @@ __global__ void __launch_bounds__(256) k_bs_untangle(const ExecDesc* __restrict_
 
 // Whole chirp-z transform in one workgroup (P <= kSingleMax), looping over the jobs.
 template <typename T, Src S, Sink K>
-__global__ void __launch_bounds__(256) k_bs_single(const ExecDesc* __restrict__ descs, FftGeom g, int max_jobs,
+__global__ void __launch_bounds__(256) k_bs_single(const ExecDesc* __restrict__ descs, const Item* __restrict__ items,
                                                    size_t acc_off)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    const ExecDesc& d = descs[blockIdx.x];
+    const ExecDesc& d = descs[items[blockIdx.x].desc];
+    const FftGeom& g = geom_of<T>(d);
     const int L = (int)g.L, P = (int)g.P;
     const int tid = threadIdx.x, nth = blockDim.x;
     const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
@@ -541,8 +596,8 @@ __global__ void __launch_bounds__(256) k_bs_single(const ExecDesc* __restrict__ 
     double* acc = reinterpret_cast<double*>(smem_raw + acc_off);
     for (int i = 0; i < kSlots; ++i) acc[i * nth + tid] = 0.0;
     const T invP = (T)1 / (T)P;
-    for (int job = 0; job < max_jobs; ++job) {
-        if (!Source<S>::valid(d, job)) break;
+    const int njobs = Source<S>::kMulti ? d.nblk * d.M : 1;
+    for (int job = 0; job < njobs; ++job) {
         for (int t = tid; t < P; t += nth)
             buf[lds_pad(t)] = t < L ? cmul(to_t<T>(Source<S>::load(d, job, t)), chirp[t]) : cx<T>{(T)0, (T)0};
         __syncthreads();
@@ -557,17 +612,7 @@ __global__ void __launch_bounds__(256) k_bs_single(const ExecDesc* __restrict__ 
             const int sx = tid + q * nth;
             if (sx >= nel) break;
             cx<double> xa, xb;
-            if (sx == 0) {
-                cx<T> z = buf[lds_pad(0)];
-                xa = {(double)z.re + (double)z.im, 0.0};
-                xb = {(double)z.re - (double)z.im, 0.0};
-            } else if (2 * sx == L) {
-                cx<T> z = buf[lds_pad(sx)];
-                xa = {(double)z.re, (double)z.im};
-                xb = xa;
-            } else {
-                untangle<T>(buf[lds_pad(sx)], buf[lds_pad(L - sx)], utw[sx], xa, xb);
-            }
+            untangle_at<T>([&](int64_t i) { return buf[lds_pad((int)i)]; }, L, sx, utw[sx], xa, xb);
             acc[(2 * q) * nth + tid] += Target<K>::contrib(d, job, sx, xa);
             if (2 * sx != L) acc[(2 * q + 1) * nth + tid] += Target<K>::contrib(d, job, L - sx, xb);
         }
@@ -582,273 +627,201 @@ __global__ void __launch_bounds__(256) k_bs_single(const ExecDesc* __restrict__ 
     }
 }
 
-// ------------------------------------------------------------------ launch
+// ------------------------------------------------------------------ host side
 
 namespace {
 
-size_t lds_bytes(int n_elems, size_t esz) { return (size_t)(n_elems + (n_elems >> 4) + 1) * esz; }
+size_t lds_bytes(int64_t n_elems, size_t esz) { return (size_t)(n_elems + (n_elems >> 4) + 1) * esz; }
+size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+int clamp_nth(int64_t F) { return (int)std::min<int64_t>(256, std::max<int64_t>(64, F / 16)); }
 
-// Workgroups of this engine use up to ~70 KB of LDS (gfx950 has 160 KB per CU);
-// raise the dynamic-LDS limit of each kernel once before its first launch.
+// Workgroups of this engine use up to ~110 KB of LDS (gfx950 has 160 KB per CU);
+// the dynamic-LDS limit of a kernel is raised once per device and size, so a
+// launch sequence replayed under stream capture makes no attribute calls.
+std::mutex g_lds_mu;
+std::map<std::pair<int, const void*>, size_t> g_lds_set;
+
 template <typename K>
 cjt_status allow_lds(K kernel, size_t bytes)
 {
-    CJT_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    int dev = 0;
+    CJT_HIP_TRY(hipGetDevice(&dev));
+    const void* f = reinterpret_cast<const void*>(kernel);
+    std::lock_guard<std::mutex> lk(g_lds_mu);
+    size_t& cur = g_lds_set[{dev, f}];
+    if (bytes <= cur) return CJT_OK;
+    CJT_HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    cur = bytes;
+    return CJT_OK;
+}
+
+template <typename K, typename... Args>
+cjt_status go(K kernel, const Launch& L, hipStream_t s, Args... args)
+{
+    if (L.nitems <= 0) return CJT_OK;
+    if (L.lds > 48 * 1024) {
+        cjt_status st = allow_lds(kernel, L.lds);
+        if (st != CJT_OK) return st;
+    }
+    ProfScope ps(L.name, L.flops, L.bytes, s);
+    hipLaunchKernelGGL(kernel, dim3((unsigned)L.nitems), dim3(L.nth), L.lds, s, args...);
+    CJT_HIP_TRY(hipGetLastError());
     return CJT_OK;
 }
 
 template <typename T, Src S, Sink K>
-cjt_status run_bs(const EngineArgs& a, int max_jobs, bool single_job)
+cjt_status run(const Launch& L, const ExecDesc* dd, const Item* it, hipStream_t s)
 {
-    const FftGeom& g = a.geom;
-    const size_t esz = sizeof(cx<T>);
-    if (g.single) {
-        const int P = (int)g.P;
-        int nth = P / 16;
-        if (nth < 64) nth = 64;
-        if (nth > 256) nth = 256;
-        if (((int)g.L / 2 + 1 + nth - 1) / nth > kSlots / 2) return fail(CJT_EUNSUPPORTED, "chirp-z length too large");
-        const size_t acc_off = (lds_bytes(P, esz) + 255) & ~(size_t)255;
-        const size_t total = acc_off + sizeof(double) * kSlots * nth;
-        cjt_status st = allow_lds(k_bs_single<T, S, K>, total);
-        if (st != CJT_OK) return st;
-        ProfScope ps(a.name1, a.flops1 + a.flops2, a.bytes1 + a.bytes2, a.stream);
-        hipLaunchKernelGGL((k_bs_single<T, S, K>), dim3(a.count), dim3(nth), total, a.stream, a.d_desc, g, max_jobs,
-                           acc_off);
-        CJT_HIP_TRY(hipGetLastError());
-        return CJT_OK;
+    constexpr bool kMulti = Source<S>::kMulti;
+    switch (L.kind) {
+    case Kind::FftSingle: return go(k_single<T, S, K>, L, s, dd, it, L.acc_off);
+    case Kind::FftPass1: return go(k_pass1<T, S>, L, s, dd, it);
+    case Kind::FftPass2: return go(k_pass2<T, K, kMulti>, L, s, dd, it, L.acc_off);
+    case Kind::BsSingle: return go(k_bs_single<T, S, K>, L, s, dd, it, L.acc_off);
+    case Kind::BsCol1: return go(k_bs_col1<T, S>, L, s, dd, it);
+    case Kind::BsRow1: return go(k_bs_row1<T>, L, s, dd, it);
+    case Kind::BsCol2: return go(k_bs_col2<T>, L, s, dd, it);
+    case Kind::BsRow2: return go(k_bs_row2<T>, L, s, dd, it);
+    case Kind::BsUntangle: return go(k_bs_untangle<T, K, kMulti>, L, s, dd, it);
+    default: return fail(CJT_EINVAL, "not an FFT launch");
     }
-    const int TC = std::max(1, 2048 / g.L1);
-    const int TR = std::max(1, 2048 / g.L2);
-    const int nth1 = TC * (g.L1 / 16), nth2 = TR * (g.L2 / 16);
-    if (g.L2 % TC != 0 || g.L1 % TR != 0 || nth1 > 256 || nth2 > 256) return fail(CJT_EUNSUPPORTED, "chirp-z split");
-    const size_t lds1 = (size_t)TC * slice_stride(g.L1) * esz, lds2 = (size_t)TR * slice_stride(g.L2) * esz;
-    cjt_status st = allow_lds(k_bs_col<T, S, 1>, lds1);
-    if (st == CJT_OK) st = allow_lds(k_bs_col<T, S, 2>, lds1);
-    if (st == CJT_OK) st = allow_lds(k_bs_row<T, S, 1>, lds2);
-    if (st == CJT_OK) st = allow_lds(k_bs_row<T, S, 2>, lds2);
-    if (st != CJT_OK) return st;
-    const dim3 gc(g.L2 / TC, max_jobs, a.count), gr(g.L1 / TR, max_jobs, a.count);
-    {
-        ProfScope ps(a.name1, 0.5 * a.flops1, 0.5 * a.bytes1, a.stream);
-        hipLaunchKernelGGL((k_bs_col<T, S, 1>), gc, dim3(nth1), lds1, a.stream, a.d_desc, g, TC, (cx<T>*)nullptr);
-        CJT_HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL((k_bs_row<T, S, 1>), gr, dim3(nth2), lds2, a.stream, a.d_desc, g, TR, (cx<T>*)nullptr,
-                           (cx<T>*)nullptr);
-        CJT_HIP_TRY(hipGetLastError());
-    }
-    {
-        ProfScope ps(a.name1, 0.5 * a.flops1, 0.5 * a.bytes1, a.stream);
-        hipLaunchKernelGGL((k_bs_col<T, S, 2>), gc, dim3(nth1), lds1, a.stream, a.d_desc, g, TC, (cx<T>*)nullptr);
-        CJT_HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL((k_bs_row<T, S, 2>), gr, dim3(nth2), lds2, a.stream, a.d_desc, g, TR, (cx<T>*)nullptr,
-                           (cx<T>*)nullptr);
-        CJT_HIP_TRY(hipGetLastError());
-    }
-    {
-        ProfScope ps(a.name2, a.flops2, a.bytes2, a.stream);
-        const dim3 gu((unsigned)((g.L / 2 + 1 + 255) / 256), a.count);
-        hipLaunchKernelGGL((k_bs_untangle<T, K>), gu, dim3(256), 0, a.stream, a.d_desc, g, single_job ? 1 : 0);
-        CJT_HIP_TRY(hipGetLastError());
-    }
-    return CJT_OK;
-}
-
-template <typename T, Src S, Sink K>
-cjt_status run(const EngineArgs& a)
-{
-    const FftGeom& g = a.geom;
-    const size_t esz = sizeof(cx<T>);
-    const bool single_job = (S != Src::FwdAsy && S != Src::InvAsy);
-    const int max_jobs = single_job ? 1 : a.max_jobs;
-    if (max_jobs <= 0 || a.count <= 0) return CJT_OK;
-    if (g.bluestein) return run_bs<T, S, K>(a, max_jobs, single_job);
-    if (g.single) {
-        const int L = (int)g.L;
-        int nth = L / 16;
-        if (nth < 64) nth = 64;
-        if (nth > 256) nth = 256;
-        if ((L / 2 + 1 + nth - 1) / nth > kSlots / 2) return fail(CJT_EUNSUPPORTED, "single-pass length too large");
-        const size_t acc_off = (lds_bytes(L, esz) + 255) & ~(size_t)255;
-        const size_t total = acc_off + sizeof(double) * kSlots * nth;
-        cjt_status st = allow_lds(k_single<T, S, K>, total);
-        if (st != CJT_OK) return st;
-        ProfScope ps(a.name1, a.flops1 + a.flops2, a.bytes1 + a.bytes2, a.stream);
-        hipLaunchKernelGGL((k_single<T, S, K>), dim3(a.count), dim3(nth), total, a.stream, a.d_desc, g, max_jobs,
-                           acc_off);
-        CJT_HIP_TRY(hipGetLastError());
-        return CJT_OK;
-    }
-    // two passes: 2048 complex values per workgroup in the column pass (TC
-    // columns of L1) and TU row pairs of L2 (at least 2048 values) in the row pass;
-    // every thread holds 16 values of one transform.
-    const int TC = std::max(1, 2048 / g.L1);
-    const int TU = std::max(1, 1024 / g.L2);
-    const int nth1 = TC * (g.L1 / 16), nth2 = 2 * TU * (g.L2 / 16);
-    if (g.L2 % TC != 0 || (g.L1 / 2) % TU != 0 || nth1 > 256 || nth2 > 256 || TU * g.L2 != nth2 * kEPT)
-        return fail(CJT_EUNSUPPORTED, "FFT split not supported");
-    const size_t lds1 = (size_t)TC * slice_stride(g.L1) * esz;
-    const size_t acc_off = ((size_t)2 * TU * slice_stride(g.L2) * esz + 255) & ~(size_t)255;
-    const size_t lds2 = acc_off + sizeof(double) * (2 * kEPT + 1) * nth2;
-    cjt_status st = allow_lds(k_pass1<T, S>, lds1);
-    if (st == CJT_OK) st = allow_lds(k_pass2<T, K>, lds2);
-    if (st != CJT_OK) return st;
-    dim3 g1(g.L2 / TC, max_jobs, a.count);
-    {
-        ProfScope ps(a.name1, a.flops1, a.bytes1, a.stream);
-        hipLaunchKernelGGL((k_pass1<T, S>), g1, dim3(nth1), lds1, a.stream, a.d_desc, g, TC);
-        CJT_HIP_TRY(hipGetLastError());
-    }
-    dim3 g2((g.L1 / 2) / TU, 1, a.count);
-    {
-        ProfScope ps(a.name2, a.flops2, a.bytes2, a.stream);
-        hipLaunchKernelGGL((k_pass2<T, K>), g2, dim3(nth2), lds2, a.stream, a.d_desc, g, TU, max_jobs,
-                           single_job ? 1 : 0, acc_off);
-        CJT_HIP_TRY(hipGetLastError());
-    }
-    return CJT_OK;
 }
 
 }  // namespace
 
-cjt_status launch_rdft(const EngineArgs& a, Src src, Sink sink, bool fp32)
+cjt_status launch_fft(const Launch& L, const ExecDesc* dd, const Item* it, hipStream_t s)
 {
-    if (src == Src::FwdAsy && sink == Sink::FwdAsy)
-        return fp32 ? run<float, Src::FwdAsy, Sink::FwdAsy>(a) : run<double, Src::FwdAsy, Sink::FwdAsy>(a);
-    if (src == Src::InvAsy && sink == Sink::InvAsy)
-        return fp32 ? run<float, Src::InvAsy, Sink::InvAsy>(a) : run<double, Src::InvAsy, Sink::InvAsy>(a);
-    if (src == Src::FwdFinal && sink == Sink::FwdFinal) return run<double, Src::FwdFinal, Sink::FwdFinal>(a);
-    if (src == Src::InvInit && sink == Sink::InvInit) return run<double, Src::InvInit, Sink::InvInit>(a);
-    if (src == Src::Moments && sink == Sink::Weights) return run<double, Src::Moments, Sink::Weights>(a);
+    const bool f = L.fp32 != 0;
+    if (L.src == Src::FwdAsy && L.sink == Sink::FwdAsy)
+        return f ? run<float, Src::FwdAsy, Sink::FwdAsy>(L, dd, it, s) : run<double, Src::FwdAsy, Sink::FwdAsy>(L, dd, it, s);
+    if (L.src == Src::InvAsy && L.sink == Sink::InvAsy)
+        return f ? run<float, Src::InvAsy, Sink::InvAsy>(L, dd, it, s) : run<double, Src::InvAsy, Sink::InvAsy>(L, dd, it, s);
+    if (f) return fail(CJT_EINVAL, "boundary transforms run in FP64");
+    if (L.src == Src::FwdFinal && L.sink == Sink::FwdFinal) return run<double, Src::FwdFinal, Sink::FwdFinal>(L, dd, it, s);
+    if (L.src == Src::InvInit && L.sink == Sink::InvInit) return run<double, Src::InvInit, Sink::InvInit>(L, dd, it, s);
+    if (L.src == Src::Moments && L.sink == Sink::Weights) return run<double, Src::Moments, Sink::Weights>(L, dd, it, s);
     return fail(CJT_EINVAL, "unknown transform pairing");
 }
 
-// chirp-z tables: c_t = e^{i pi t^2 / L} (t < L), utw_s = e^{i pi s / L} (s <= L)
-template <typename T>
-__global__ void k_chirp_tables(cx<T>* chirp, cx<T>* utw, int64_t L)
+// Launch classes of one engine pass: instances are bucketed by kernel and
+// workgroup size; each bucket is one launch over its items.
+cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sink, bool fp32, int stream,
+                   const char* name_cols, const char* name_rows, const std::vector<double>& flops,
+                   const std::vector<double>& bytes)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t > L) return;
-    double sn, cs;
-    if (t < L) {
-        const int64_t r = (t * t) % (2 * L);  // exact angle reduction
-        sincospi((double)r / (double)L, &sn, &cs);
-        chirp[t] = {(T)cs, (T)sn};
+    const bool multi = (src == Src::FwdAsy || src == Src::InvAsy);
+    const bool f32 = fp32 && multi;
+    const size_t esz = f32 ? sizeof(cx<float>) : sizeof(cx<double>);
+    struct Bucket {
+        Kind kind;
+        int nth;
+        std::vector<Item> items;
+        size_t lds = 0, acc = 0;
+        double flops = 0, bytes = 0;
+        const char* name;
+    };
+    std::vector<Bucket> bk;
+    auto bucket = [&](Kind k, int nth, const char* nm) -> Bucket& {
+        for (auto& b : bk)
+            if (b.kind == k && b.nth == nth) return b;
+        bk.push_back(Bucket{k, nth, {}, 0, 0, 0, 0, nm});
+        return bk.back();
+    };
+    for (int i : which) {
+        const ExecDesc& d = pr.descs[i];
+        const FftGeom& g = f32 ? d.geob : d.geo;
+        const int jobs = multi ? d.nblk * d.M : 1;
+        if (jobs <= 0) continue;
+        const double fl = flops[i], by = bytes[i];
+        if (!g.bluestein && g.single) {
+            const int nth = clamp_nth(g.L);
+            if ((g.L / 2 + 1 + nth - 1) / nth > kSlots / 2) return fail(CJT_EUNSUPPORTED, "single-pass length");
+            Bucket& b = bucket(Kind::FftSingle, nth, name_cols);
+            b.items.push_back(Item{i, 0, 0, 0});
+            b.acc = std::max(b.acc, a256(lds_bytes(g.L, esz)));
+            b.flops += fl;
+            b.bytes += by;
+        } else if (!g.bluestein) {
+            if (g.L1 > 2048 || g.L2 > 2048) return fail(CJT_EUNSUPPORTED, "FFT length too large");
+            const int TC = g.L1 >= 2048 ? 1 : 2048 / g.L1;
+            const int TU = g.L2 >= 1024 ? 1 : 1024 / g.L2;
+            const int nth2 = 2 * TU * (g.L2 / 16);
+            Bucket& b1 = bucket(Kind::FftPass1, 128, name_cols);
+            for (int j = 0; j < jobs; ++j)
+                for (int t = 0; t < g.L2 / TC; ++t) b1.items.push_back(Item{i, j, t, 0});
+            b1.lds = std::max(b1.lds, (size_t)TC * slice_stride(g.L1) * esz);
+            b1.flops += 0.5 * fl;
+            b1.bytes += 0.5 * by;
+            Bucket& b2 = bucket(Kind::FftPass2, nth2, name_rows);
+            for (int t = 0; t < (g.L1 / 2) / TU; ++t) b2.items.push_back(Item{i, 0, t, 0});
+            b2.acc = std::max(b2.acc, a256((size_t)2 * TU * slice_stride(g.L2) * esz));
+            b2.flops += 0.5 * fl;
+            b2.bytes += 0.5 * by;
+        } else if (g.single) {
+            const int nth = clamp_nth(g.P);
+            if ((g.L / 2 + 1 + nth - 1) / nth > kSlots / 2) return fail(CJT_EUNSUPPORTED, "chirp-z length");
+            Bucket& b = bucket(Kind::BsSingle, nth, name_cols);
+            b.items.push_back(Item{i, 0, 0, 0});
+            b.acc = std::max(b.acc, a256(lds_bytes(g.P, esz)));
+            b.flops += fl;
+            b.bytes += by;
+        } else {
+            if (g.L1 > 2048 || g.L2 > 4096) return fail(CJT_EUNSUPPORTED, "chirp-z length too large");
+            const int TC = g.L1 >= 2048 ? 1 : 2048 / g.L1;
+            const int TR = g.L2 >= 2048 ? 1 : 2048 / g.L2;
+            const int nthr = TR * (g.L2 / 16);
+            const Kind ks[4] = {Kind::BsCol1, Kind::BsRow1, Kind::BsCol2, Kind::BsRow2};
+            for (int q = 0; q < 4; ++q) {
+                const bool col = (q % 2) == 0;
+                Bucket& b = bucket(ks[q], col ? 128 : nthr, name_cols);
+                const int tiles = col ? g.L2 / TC : g.L1 / TR;
+                for (int j = 0; j < jobs; ++j)
+                    for (int t = 0; t < tiles; ++t) b.items.push_back(Item{i, j, t, 0});
+                b.lds = std::max(b.lds, col ? (size_t)TC * slice_stride(g.L1) * esz : (size_t)TR * slice_stride(g.L2) * esz);
+                b.flops += 0.125 * fl;
+                b.bytes += 0.125 * by;
+            }
+            Bucket& bu = bucket(Kind::BsUntangle, 256, name_rows);
+            for (int64_t t = 0; t < (g.L / 2 + 1 + 255) / 256; ++t) bu.items.push_back(Item{i, 0, (int32_t)t, 0});
+            bu.flops += 0.5 * fl;
+            bu.bytes += 0.5 * by;
+        }
     }
-    sincospi((double)t / (double)L, &sn, &cs);
-    utw[t] = {(T)cs, (T)sn};
-}
-
-template <typename T>
-__global__ void k_to_float(const cx<double>* in, cx<float>* out, int64_t n)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = {(float)in[i].re, (float)in[i].im};
-}
-
-// F(b~) in one workgroup for P <= kSingleMax
-__global__ void __launch_bounds__(256) k_bl_single(FftGeom g, cx<double>* bl)
-{
-    extern __shared__ unsigned char smem_raw[];
-    cx<double>* buf = reinterpret_cast<cx<double>*>(smem_raw);
-    const int64_t P = g.P, L = g.L;
-    const cx<double>* chirp = reinterpret_cast<const cx<double>*>(g.chirp);
-    const cx<double>* tw = reinterpret_cast<const cx<double>*>(g.tw);
-    for (int64_t t = threadIdx.x; t < P; t += blockDim.x) {
-        cx<double> x = {0.0, 0.0};
-        if (t < L) x = conj(chirp[t]);
-        else if (t > P - L) x = conj(chirp[P - t]);
-        buf[lds_pad((int)t)] = x;
+    // launch order: single-workgroup kinds, then the two-pass chains in dependency order
+    const Kind order[] = {Kind::FftSingle, Kind::BsSingle, Kind::FftPass1, Kind::FftPass2, Kind::BsCol1,
+                          Kind::BsRow1,    Kind::BsCol2,   Kind::BsRow2,   Kind::BsUntangle};
+    for (Kind k : order) {
+        for (auto& b : bk) {
+            if (b.kind != k || b.items.empty()) continue;
+            Launch L;
+            L.kind = k;
+            L.stream = stream;
+            L.src = src;
+            L.sink = sink;
+            L.fp32 = f32 ? 1 : 0;
+            L.nth = b.nth;
+            L.item_off = (int64_t)pr.items.size();
+            L.nitems = (int64_t)b.items.size();
+            if (k == Kind::FftSingle || k == Kind::BsSingle) {
+                L.acc_off = b.acc;
+                L.lds = b.acc + sizeof(double) * kSlots * b.nth;
+            } else if (k == Kind::FftPass2) {
+                L.acc_off = b.acc;
+                L.lds = b.acc + sizeof(double) * (2 * kEPT + 1) * b.nth;
+            } else {
+                L.lds = b.lds;
+            }
+            L.name = b.name;
+            L.flops = b.flops;
+            L.bytes = b.bytes;
+            pr.items.insert(pr.items.end(), b.items.begin(), b.items.end());
+            pr.launches.push_back(L);
+        }
     }
-    __syncthreads();
-    lds_fft<double>(buf, g.logP, 1, tw, 2 * P);
-    for (int64_t t = threadIdx.x; t < P; t += blockDim.x) bl[t] = buf[lds_pad((int)t)];
-}
-
-// Builds chirp, utw and F(b~) for g (whose L, P, split and tw are set), in FP64
-// and, if fp32, converts them.  Device memory is owned by the caller's cache.
-cjt_status make_chirp_tables(FftGeom* g, bool fp32, hipStream_t st)
-{
-    const int64_t L = g->L, P = g->P;
-    cx<double>* chirp = nullptr;
-    cx<double>* utw = nullptr;
-    cx<double>* bl = nullptr;
-    CJT_HIP_TRY(hipMalloc(&chirp, sizeof(cx<double>) * L));
-    CJT_HIP_TRY(hipMalloc(&utw, sizeof(cx<double>) * (L + 1)));
-    CJT_HIP_TRY(hipMalloc(&bl, sizeof(cx<double>) * P));
-    hipLaunchKernelGGL(k_chirp_tables<double>, dim3((unsigned)((L + 1 + 255) / 256)), dim3(256), 0, st, chirp, utw, L);
-    CJT_HIP_TRY(hipGetLastError());
-    FftGeom g64 = *g;
-    g64.chirp = chirp;
-    g64.utw = utw;
-    const void* tw64 = nullptr;
-    cjt_status s = CJT_OK;
-    if (fp32) {
-        // the kernel spectrum is always formed in FP64
-        s = fft_twiddles_cached(P, false, st, &tw64);
-        if (s != CJT_OK) return s;
-        g64.tw = tw64;
-    }
-    if (g->single) {
-        const size_t lds = lds_bytes((int)P, sizeof(cx<double>));
-        s = allow_lds(k_bl_single, lds);
-        if (s != CJT_OK) return s;
-        hipLaunchKernelGGL(k_bl_single, dim3(1), dim3(256), lds, st, g64, bl);
-        CJT_HIP_TRY(hipGetLastError());
-    } else {
-        cx<double>* scratch = nullptr;
-        CJT_HIP_TRY(hipMalloc(&scratch, sizeof(cx<double>) * P));
-        const int TC = std::max(1, 2048 / g->L1), TR = std::max(1, 2048 / g->L2);
-        const int nth1 = TC * (g->L1 / 16), nth2 = TR * (g->L2 / 16);
-        const size_t lds1 = (size_t)TC * slice_stride(g->L1) * 16, lds2 = (size_t)TR * slice_stride(g->L2) * 16;
-        s = allow_lds(k_bs_col<double, Src::FwdAsy, 0>, lds1);
-        if (s == CJT_OK) s = allow_lds(k_bs_row<double, Src::FwdAsy, 0>, lds2);
-        if (s != CJT_OK) return s;
-        hipLaunchKernelGGL((k_bs_col<double, Src::FwdAsy, 0>), dim3(g->L2 / TC, 1, 1), dim3(nth1), lds1, st,
-                           (const ExecDesc*)nullptr, g64, TC, scratch);
-        CJT_HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL((k_bs_row<double, Src::FwdAsy, 0>), dim3(g->L1 / TR, 1, 1), dim3(nth2), lds2, st,
-                           (const ExecDesc*)nullptr, g64, TR, scratch, bl);
-        CJT_HIP_TRY(hipGetLastError());
-        CJT_HIP_TRY(hipStreamSynchronize(st));
-        CJT_HIP_TRY(hipFree(scratch));
-    }
-    if (!fp32) {
-        g->chirp = chirp;
-        g->utw = utw;
-        g->bl = bl;
-    } else {
-        cx<float>* c32 = nullptr;
-        cx<float>* u32 = nullptr;
-        cx<float>* b32 = nullptr;
-        CJT_HIP_TRY(hipMalloc(&c32, sizeof(cx<float>) * L));
-        CJT_HIP_TRY(hipMalloc(&u32, sizeof(cx<float>) * (L + 1)));
-        CJT_HIP_TRY(hipMalloc(&b32, sizeof(cx<float>) * P));
-        hipLaunchKernelGGL(k_to_float<float>, dim3((unsigned)((L + 255) / 256)), dim3(256), 0, st, chirp, c32, L);
-        hipLaunchKernelGGL(k_to_float<float>, dim3((unsigned)((L + 256) / 256)), dim3(256), 0, st, utw, u32, L + 1);
-        hipLaunchKernelGGL(k_to_float<float>, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, bl, b32, P);
-        CJT_HIP_TRY(hipGetLastError());
-        CJT_HIP_TRY(hipStreamSynchronize(st));
-        CJT_HIP_TRY(hipFree(chirp));
-        CJT_HIP_TRY(hipFree(utw));
-        CJT_HIP_TRY(hipFree(bl));
-        g->chirp = c32;
-        g->utw = u32;
-        g->bl = b32;
-    }
-    CJT_HIP_TRY(hipStreamSynchronize(st));
     return CJT_OK;
 }
 
-size_t fft_job_bytes(int64_t L, bool fp32)
-{
-    const size_t esz = fp32 ? 8 : 16;
-    if ((L & (L - 1)) == 0) return L > kSingleMax ? esz * (size_t)L : 0;
-    int64_t P = 1;
-    while (P < 2 * L - 1) P <<= 1;
-    return P > kSingleMax ? esz * (size_t)(2 * P + L) : 0;
-}
+// ------------------------------------------------------------------ tables
 
 // tw[q] = exp(i pi q / L), q < 2L
 template <typename T>
@@ -873,6 +846,148 @@ cjt_status make_twiddles(int64_t L, bool fp32, const void** out, hipStream_t str
     CJT_HIP_TRY(hipGetLastError());
     *out = p;
     return CJT_OK;
+}
+
+// chirp-z tables: c_t = e^{i pi t^2 / L} (t < L), utw_s = e^{i pi s / L} (s <= L);
+// the angle t^2 / L is reduced modulo 2 in exact integer arithmetic.
+__global__ void k_chirp_tables(cx<double>* chirp, cx<double>* utw, int64_t L)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > L) return;
+    double sn, cs;
+    if (t < L) {
+        const int64_t r = (t * t) % (2 * L);
+        sincospi((double)r / (double)L, &sn, &cs);
+        chirp[t] = {cs, sn};
+    }
+    sincospi((double)t / (double)L, &sn, &cs);
+    utw[t] = {cs, sn};
+}
+
+__global__ void k_to_float(const cx<double>* in, cx<float>* out, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = {(float)in[i].re, (float)in[i].im};
+}
+
+// b~_t = conj(c_|k|) wrapped cyclically: t < L, or t > P - L (k = P - t)
+__device__ __forceinline__ cx<double> bl_input(const cx<double>* chirp, int64_t L, int64_t P, int64_t t)
+{
+    if (t < L) return conj(chirp[t]);
+    if (t > P - L) return conj(chirp[P - t]);
+    return {0.0, 0.0};
+}
+
+// F(b~) in one workgroup for P <= kSingleMax
+__global__ void __launch_bounds__(256) k_bl_single(FftGeom g, cx<double>* bl)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<double>* buf = reinterpret_cast<cx<double>*>(smem_raw);
+    const int64_t P = g.P, L = g.L;
+    const cx<double>* chirp = reinterpret_cast<const cx<double>*>(g.chirp);
+    for (int64_t t = threadIdx.x; t < P; t += blockDim.x) buf[lds_pad((int)t)] = bl_input(chirp, L, P, t);
+    __syncthreads();
+    lds_fft<double>(buf, g.logP, 1, reinterpret_cast<const cx<double>*>(g.tw), 2 * P);
+    for (int64_t t = threadIdx.x; t < P; t += blockDim.x) bl[t] = buf[lds_pad((int)t)];
+}
+
+__global__ void __launch_bounds__(128) k_bl_col(FftGeom g, cx<double>* scratch)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const cx<double>* chirp = reinterpret_cast<const cx<double>*>(g.chirp);
+    const int64_t P = g.P, L = g.L;
+    col_pass<double>(
+        reinterpret_cast<cx<double>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<double>*>(g.tw),
+        blockIdx.x, [&](int64_t t) { return bl_input(chirp, L, P, t); }, [&](int64_t i, cx<double> v) { scratch[i] = v; });
+}
+
+__global__ void __launch_bounds__(256) k_bl_row(FftGeom g, const cx<double>* scratch, cx<double>* bl)
+{
+    extern __shared__ unsigned char smem_raw[];
+    row_pass<double>(
+        reinterpret_cast<cx<double>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<double>*>(g.tw),
+        blockIdx.x, [&](int64_t i) { return scratch[i]; }, [&](int64_t i, cx<double> v) { bl[i] = v; });
+}
+
+// Builds chirp, utw and F(b~) for g (whose L, P, split and tw are set), in FP64
+// and, if fp32, converted.  The device memory belongs to the geometry cache.
+cjt_status make_chirp_tables(FftGeom* g, bool fp32, hipStream_t st)
+{
+    const int64_t L = g->L, P = g->P;
+    cx<double>* chirp = nullptr;
+    cx<double>* utw = nullptr;
+    cx<double>* bl = nullptr;
+    CJT_HIP_TRY(hipMalloc(&chirp, sizeof(cx<double>) * L));
+    CJT_HIP_TRY(hipMalloc(&utw, sizeof(cx<double>) * (L + 1)));
+    CJT_HIP_TRY(hipMalloc(&bl, sizeof(cx<double>) * P));
+    hipLaunchKernelGGL(k_chirp_tables, dim3((unsigned)((L + 1 + 255) / 256)), dim3(256), 0, st, chirp, utw, L);
+    CJT_HIP_TRY(hipGetLastError());
+    FftGeom g64 = *g;
+    g64.chirp = chirp;
+    g64.utw = utw;
+    cjt_status s = CJT_OK;
+    if (fp32) {  // the kernel spectrum is always formed in FP64
+        const void* tw64 = nullptr;
+        s = fft_twiddles_cached(P, false, st, &tw64);
+        if (s != CJT_OK) return s;
+        g64.tw = tw64;
+    }
+    if (g->single) {
+        const size_t lds = lds_bytes(P, sizeof(cx<double>));
+        s = allow_lds(k_bl_single, lds);
+        if (s != CJT_OK) return s;
+        hipLaunchKernelGGL(k_bl_single, dim3(1), dim3(256), lds, st, g64, bl);
+        CJT_HIP_TRY(hipGetLastError());
+    } else {
+        cx<double>* scratch = nullptr;
+        CJT_HIP_TRY(hipMalloc(&scratch, sizeof(cx<double>) * P));
+        const int TC = g->L1 >= 2048 ? 1 : 2048 / g->L1, TR = g->L2 >= 2048 ? 1 : 2048 / g->L2;
+        const size_t lds1 = (size_t)TC * slice_stride(g->L1) * sizeof(cx<double>);
+        const size_t lds2 = (size_t)TR * slice_stride(g->L2) * sizeof(cx<double>);
+        s = allow_lds(k_bl_col, lds1);
+        if (s == CJT_OK) s = allow_lds(k_bl_row, lds2);
+        if (s != CJT_OK) return s;
+        hipLaunchKernelGGL(k_bl_col, dim3(g->L2 / TC), dim3(128), lds1, st, g64, scratch);
+        CJT_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_bl_row, dim3(g->L1 / TR), dim3(TR * (g->L2 / 16)), lds2, st, g64, scratch, bl);
+        CJT_HIP_TRY(hipGetLastError());
+        CJT_HIP_TRY(hipStreamSynchronize(st));
+        CJT_HIP_TRY(hipFree(scratch));
+    }
+    if (!fp32) {
+        g->chirp = chirp;
+        g->utw = utw;
+        g->bl = bl;
+    } else {
+        cx<float>* c32 = nullptr;
+        cx<float>* u32 = nullptr;
+        cx<float>* b32 = nullptr;
+        CJT_HIP_TRY(hipMalloc(&c32, sizeof(cx<float>) * L));
+        CJT_HIP_TRY(hipMalloc(&u32, sizeof(cx<float>) * (L + 1)));
+        CJT_HIP_TRY(hipMalloc(&b32, sizeof(cx<float>) * P));
+        hipLaunchKernelGGL(k_to_float, dim3((unsigned)((L + 255) / 256)), dim3(256), 0, st, chirp, c32, L);
+        hipLaunchKernelGGL(k_to_float, dim3((unsigned)((L + 256) / 256)), dim3(256), 0, st, utw, u32, L + 1);
+        hipLaunchKernelGGL(k_to_float, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, bl, b32, P);
+        CJT_HIP_TRY(hipGetLastError());
+        CJT_HIP_TRY(hipStreamSynchronize(st));
+        CJT_HIP_TRY(hipFree(chirp));
+        CJT_HIP_TRY(hipFree(utw));
+        CJT_HIP_TRY(hipFree(bl));
+        g->chirp = c32;
+        g->utw = u32;
+        g->bl = b32;
+    }
+    CJT_HIP_TRY(hipStreamSynchronize(st));
+    return CJT_OK;
+}
+
+size_t fft_job_bytes(int64_t L, bool fp32)
+{
+    const size_t esz = fp32 ? 8 : 16;
+    if ((L & (L - 1)) == 0) return L > kSingleMax ? esz * (size_t)L : 0;
+    int64_t P = 1;
+    while (P < 2 * L - 1) P <<= 1;
+    return P > kSingleMax ? esz * (size_t)(2 * P) : 0;
 }
 
 }  // namespace cjt

@@ -31,6 +31,11 @@
 // A_n x + B_n to FP64 first would act like a rounded point again (it costs
 // about a factor 10 in the inverse when the recurrence covers the whole
 // matrix).  What remains is the per-step rounding of the recurrence itself.
+#include <stdlib.h>
+
+#include <algorithm>
+#include <cmath>
+
 #include "cjt_internal.h"
 
 namespace cjt {
@@ -116,18 +121,37 @@ __device__ void grid_point(int64_t i, int64_t G, int mode, double& hi, double& l
 
 }  // namespace
 
-constexpr int kPPT = 4;     // points per thread, inverse
+constexpr int kPPT = 4;     // points per lane (tasks are at most 64 * kPPT points)
 constexpr int kChunk = 16;  // degrees per LDS reduction round (divides kBlk)
+constexpr int kBlk = 128;   // degrees per LDS coefficient block
+constexpr int kRec = 6 * 64 * kPPT;  // doubles per segment record (6 per point)
 
-// ------------------------------------------------------------------ forward
+// ------------------------------------------------------------------ segments
+//
+// A task whose degree range [0, cut) is long would be one serial chain of cut
+// steps.  With a segment length S (chosen per call from the total work), a
+// task with cut > 2S is split into nseg = ceil(cut / S) segments of equal
+// length (rounded up to kBlk).  Every recurrence here is linear in its
+// two-term state, so a segment maps the state entering it to the state
+// leaving it by an affine map (forward: Clenshaw run downward, with the
+// coefficients c_n) or a linear one (inverse: the recurrence run upward).
+// Segments compute their maps in parallel (two extra homogeneous chains),
+// and a short serial pass per point chains them.
 
-// Each lane carries kPPTF points of the task (up to 64*kPPTF points, one
-// recurrence per point).  The per-degree coefficients (a d4 record and c_n)
-// are staged through LDS in blocks of kBlk degrees with coalesced vector
-// loads; the loads of the next block are issued before the current block is
-// consumed, so the serial chain never waits on memory latency.
-constexpr int kPPTF = 4;
-constexpr int kBlk = 128;
+__host__ __device__ __forceinline__ int seg_count(int cut, int S) { return cut > 2 * S ? (cut + S - 1) / S : 1; }
+
+__host__ __device__ __forceinline__ int seg_len(int cut, int nseg)
+{
+    const int l = (cut + nseg - 1) / nseg;
+    return (l + kBlk - 1) / kBlk * kBlk;
+}
+
+// ------------------------------------------------------------------ coefficient staging
+//
+// The per-degree coefficients (a d4 record and c_n) are staged through LDS in
+// blocks of kBlk degrees with coalesced vector loads; the loads of the next
+// block are issued before the current block is consumed, so the serial chain
+// never waits on memory latency.
 
 struct Stage {
     d4 co[kBlk];
@@ -166,206 +190,468 @@ __device__ __forceinline__ void stage_store(Stage& st, const StageRegs& r, int l
     }
 }
 
-__global__ void __launch_bounds__(64) k_rec_fwd(const ExecDesc* __restrict__ descs)
+struct TaskView {
+    int p0, np, mode, cut;
+    int64_t off;
+};
+
+__device__ __forceinline__ TaskView task_of(const ExecDesc& d, int t)
+{
+    cptr<RecTask> tp = as_const(d.tasks) + t;
+    return TaskView{uniform(tp->p0), uniform(tp->np), uniform(tp->mode), uniform(tp->cut), tp->off};
+}
+
+// ------------------------------------------------------------------ forward
+
+// Item (desc, task, segment, record slot).  kSplit = false: the whole range
+// [0, cut) of the task, result written to p.  kSplit = true: one segment;
+// chain 0 runs from a zero state with c_n (the affine part), chains 1 and 2
+// from the unit states without c_n (the linear part); the three final states
+// go to the segment's record.
+template <bool kSplit>
+__global__ void __launch_bounds__(64) k_rec_fwd(const ExecDesc* __restrict__ descs, const Item* __restrict__ items,
+                                                int S)
 {
     __shared__ Stage stg[2];
-    const ExecDesc& d = descs[blockIdx.x];
-    const int task = blockIdx.y;
-    if (task >= d.ntasks) return;
-    cptr<RecTask> tp = as_const(d.tasks) + task;
-    const int p0 = uniform(tp->p0), np = uniform(tp->np), mode = uniform(tp->mode), cut = uniform(tp->cut);
+    const Item it = items[blockIdx.x];
+    const ExecDesc& d = descs[it.desc];
+    const TaskView tk = task_of(d, it.a);
     const int lane = threadIdx.x;
-    const int64_t N = d.N;
-    const double* __restrict__ c = d.in;
-    const d4* __restrict__ co = mode == 0 ? d.rec0 : (mode > 0 ? d.recp : d.recm);
-    // plain: (A_n, B_n, C_{n+1});  modified: (A_n, C_{n+1} r_{n+1}, 1/r_n)
-    double xh[kPPTF], xl[kPPTF], s1[kPPTF], s2[kPPTF];
-    for (int q = 0; q < kPPTF; ++q) {
-        const int idx = lane + 64 * q;
-        const int64_t i = p0 + (idx < np ? idx : 0);
-        grid_point(i, N, mode, xh[q], xl[q]);
-        s1[q] = 0.0;  // plain: u_{n+1};  modified: u_{n+1}
-        s2[q] = 0.0;  // plain: u_{n+2};  modified: D_{n+1}
+    int lo = 0, hi = tk.cut;
+    if (kSplit) {
+        const int sl = seg_len(tk.cut, seg_count(tk.cut, S));
+        lo = it.b * sl;
+        hi = min(tk.cut, lo + sl);
     }
-    // blocks cover [b0, b0 + kBlk) with b0 descending from the top
-    const int nblk = (cut + kBlk - 1) / kBlk;
+    const int mode = tk.mode;
+    const d4* __restrict__ co = mode == 0 ? d.rec0 : (mode > 0 ? d.recp : d.recm);
+    constexpr int NC = kSplit ? 3 : 1;
+    // plain: (A_n, B_n, C_{n+1});  modified: (A_n, C_{n+1} r_{n+1}, 1/r_n)
+    double xh[kPPT], xl[kPPT], s1[NC][kPPT], s2[NC][kPPT];
+    for (int q = 0; q < kPPT; ++q) {
+        const int idx = lane + 64 * q;
+        const int64_t i = tk.p0 + (idx < tk.np ? idx : 0);
+        grid_point(i, d.N, mode, xh[q], xl[q]);
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) {
+            s1[ch][q] = ch == 1 ? 1.0 : 0.0;  // plain: u_{n+1};  modified: u_{n+1}
+            s2[ch][q] = ch == 2 ? 1.0 : 0.0;  // plain: u_{n+2};  modified: D_{n+1}
+        }
+    }
+    // blocks cover [lo + b kBlk, ...) with b descending from the top
+    const int nb = (hi - lo + kBlk - 1) / kBlk;
     StageRegs rg;
     int buf = 0;
-    if (nblk > 0) {
-        stage_load(rg, co, c, (nblk - 1) * kBlk, 0, cut, lane);
+    if (nb > 0) {
+        stage_load(rg, co, d.in, lo + (nb - 1) * kBlk, lo, hi, lane);
         stage_store(stg[0], rg, lane);
     }
     __syncthreads();
-    for (int b = nblk - 1; b >= 0; --b) {
-        const int b0 = b * kBlk;
-        if (b > 0) stage_load(rg, co, c, b0 - kBlk, 0, cut, lane);
-        const Stage& S = stg[buf];
-        const int top = min(kBlk, cut - b0) - 1;
+    for (int b = nb - 1; b >= 0; --b) {
+        const int b0 = lo + b * kBlk;
+        if (b > 0) stage_load(rg, co, d.in, b0 - kBlk, lo, hi, lane);
+        const Stage& St = stg[buf];
+        const int top = min(kBlk, hi - b0) - 1;
         if (mode == 0) {
-#pragma unroll 8
+#pragma unroll 4
             for (int t = top; t >= 0; --t) {
-                const d4 q4 = S.co[t];
-                const double cn = S.c[t];
+                const d4 q4 = St.co[t];
+                const double cn = St.c[t];
 #pragma unroll
-                for (int q = 0; q < kPPTF; ++q) {
-                    const double w = fma(xh[q], s1[q], xl[q] * s1[q]);
-                    const double u0 = fma(q4.x, w, fma(q4.y, s1[q], fma(-q4.z, s2[q], cn)));
-                    s2[q] = s1[q];
-                    s1[q] = u0;
-                }
+                for (int ch = 0; ch < NC; ++ch)
+#pragma unroll
+                    for (int q = 0; q < kPPT; ++q) {
+                        const double w = fma(xh[q], s1[ch][q], xl[q] * s1[ch][q]);
+                        const double u0 = fma(q4.x, w, fma(q4.y, s1[ch][q], fma(-q4.z, s2[ch][q], ch == 0 ? cn : 0.0)));
+                        s2[ch][q] = s1[ch][q];
+                        s1[ch][q] = u0;
+                    }
             }
         } else {
-#pragma unroll 8
+#pragma unroll 4
             for (int t = top; t >= 0; --t) {
-                const d4 q4 = S.co[t];
-                const double cn = S.c[t];
+                const d4 q4 = St.co[t];
+                const double cn = St.c[t];
                 const bool last = (b0 + t) == 0;
 #pragma unroll
-                for (int q = 0; q < kPPTF; ++q) {
-                    const double w = fma(xh[q], s1[q], xl[q] * s1[q]);
-                    const double Dn = fma(q4.x, w, fma(q4.y, s2[q], cn));
-                    if (!last) s1[q] = fma(s1[q], q4.z, Dn);
-                    s2[q] = Dn;
-                }
+                for (int ch = 0; ch < NC; ++ch)
+#pragma unroll
+                    for (int q = 0; q < kPPT; ++q) {
+                        const double w = fma(xh[q], s1[ch][q], xl[q] * s1[ch][q]);
+                        const double Dn = fma(q4.x, w, fma(q4.y, s2[ch][q], ch == 0 ? cn : 0.0));
+                        if (!last) s1[ch][q] = fma(s1[ch][q], q4.z, Dn);
+                        s2[ch][q] = Dn;
+                    }
             }
         }
         if (b > 0) stage_store(stg[buf ^ 1], rg, lane);
         __syncthreads();
         buf ^= 1;
     }
+    if (!kSplit) {
 #pragma unroll
-    for (int q = 0; q < kPPTF; ++q) {
-        const int idx = lane + 64 * q;
-        if (idx < np) d.p[p0 + idx] = mode == 0 ? s1[q] : s2[q];
+        for (int q = 0; q < kPPT; ++q) {
+            const int idx = lane + 64 * q;
+            if (idx < tk.np) d.p[tk.p0 + idx] = mode == 0 ? s1[0][q] : s2[0][q];
+        }
+    } else {
+        double* rec = d.seg + (int64_t)it.c * kRec;
+#pragma unroll
+        for (int q = 0; q < kPPT; ++q) {
+            const int idx = lane + 64 * q;
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch) {
+                rec[(2 * ch) * 64 * kPPT + idx] = s1[ch][q];
+                rec[(2 * ch + 1) * 64 * kPPT + idx] = s2[ch][q];
+            }
+        }
     }
 }
 
-cjt_status launch_rec_fwd(const EngineArgs& a)
+// Item (desc, task, nseg, first slot): state (u, s2) entering the top segment
+// is zero; each segment, from the top, maps it to
+//     state' = affine + u * unit1 + s2 * unit2,
+// and the bottom segment's result is u_0 (three-term) or D_0 (modified).
+__global__ void __launch_bounds__(64) k_rec_fwd_combine(const ExecDesc* __restrict__ descs,
+                                                        const Item* __restrict__ items)
 {
-    if (a.count <= 0 || a.max_tasks <= 0) return CJT_OK;
-    dim3 grid(a.count, a.max_tasks);
-    hipLaunchKernelGGL(k_rec_fwd, grid, dim3(64), 0, a.stream, a.d_desc);
-    CJT_HIP_TRY(hipGetLastError());
-    return CJT_OK;
+    const Item it = items[blockIdx.x];
+    const ExecDesc& d = descs[it.desc];
+    const TaskView tk = task_of(d, it.a);
+    const int nseg = it.b;
+    constexpr int R = 64 * kPPT;
+    for (int q = 0; q < kPPT; ++q) {
+        const int idx = threadIdx.x + 64 * q;
+        double x = 0.0, y = 0.0;
+#pragma unroll 4
+        for (int s = nseg - 1; s >= 0; --s) {
+            const double* rec = d.seg + (int64_t)(it.c + s) * kRec + idx;
+            const double nx = rec[0] + fma(rec[2 * R], x, rec[4 * R] * y);
+            const double ny = rec[R] + fma(rec[3 * R], x, rec[5 * R] * y);
+            x = nx;
+            y = ny;
+        }
+        if (idx < tk.np) d.p[tk.p0 + idx] = tk.mode == 0 ? x : y;
+    }
 }
 
 // ------------------------------------------------------------------ inverse
 
-__global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ descs)
+// Item (desc, task, segment, record slot), degrees [lo, hi) of the task.
+// kMaps: the two unit states are run through the segment and the final
+// states stored (records 0..3).  Otherwise the state entering the segment is
+// (g_j, 0) for an unsplit task or records 4, 5 of the slot, and each degree's
+// values are summed over the task's points into part[off + n].
+template <bool kMaps>
+__global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ descs, const Item* __restrict__ items,
+                                                int S)
 {
     __shared__ double red[kChunk][64 + 1];
     __shared__ Stage stg[2];
-    const ExecDesc& d = descs[blockIdx.x];
-    const int task = blockIdx.y;
-    if (task >= d.ntasks) return;
-    cptr<RecTask> tp = as_const(d.tasks) + task;
-    const int p0 = uniform(tp->p0), np = uniform(tp->np), mode = uniform(tp->mode), cut = uniform(tp->cut);
-    const int64_t off = tp->off;
+    const Item it = items[blockIdx.x];
+    const ExecDesc& d = descs[it.desc];
+    const TaskView tk = task_of(d, it.a);
     const int lane = threadIdx.x;
     const int64_t G = d.G;
-    double* __restrict__ part = d.part + off;
+    const bool split = it.c >= 0;
+    int lo = 0, hi = tk.cut;
+    if (split) {
+        const int sl = seg_len(tk.cut, seg_count(tk.cut, S));
+        lo = it.b * sl;
+        hi = min(tk.cut, lo + sl);
+    }
+    const int mode = tk.mode;
+    double* __restrict__ part = d.part + tk.off;
+    constexpr int NC = kMaps ? 2 : 1;
+    constexpr int R = 64 * kPPT;
+    double* rec = split ? d.seg + (int64_t)it.c * kRec : nullptr;
 
-    double pv[kPPT], ev[kPPT], xh[kPPT], xl[kPPT];
+    double pv[NC][kPPT], ev[NC][kPPT], xh[kPPT], xl[kPPT];
     for (int q = 0; q < kPPT; ++q) {
         const int idx = lane + 64 * q;
-        const bool act = idx < np;
-        const int64_t j = p0 + (act ? idx : 0);
-        const double g = act ? d.p[j] : 0.0;
-        pv[q] = g;      // pi_0 = g_j (scaled recurrence)
-        ev[q] = 0.0;    // e_0 = 0 (modified) / P_{-1} = 0 (three-term)
+        const bool act = idx < tk.np;
+        const int64_t j = tk.p0 + (act ? idx : 0);
+        if (kMaps) {
+            pv[0][q] = 1.0;
+            ev[0][q] = 0.0;
+            pv[NC - 1][q] = 0.0;
+            ev[NC - 1][q] = 1.0;
+        } else if (split) {
+            pv[0][q] = rec[4 * R + idx];
+            ev[0][q] = rec[5 * R + idx];
+        } else {
+            pv[0][q] = act ? d.p[j] : 0.0;  // pi_0 = g_j (scaled recurrence)
+            ev[0][q] = 0.0;                 // e_0 = 0 (modified) / P_{-1} = 0 (three-term)
+        }
         grid_point(j, G, mode, xh[q], xl[q]);
     }
     // three-term: (A_n, B_n, C_n);  modified: (A_n, C_n / r_{n-1}, r_n)
     const d4* __restrict__ co = mode == 0 ? d.rec0 : (mode > 0 ? d.recp : d.recm);
     const int dd = lane >> 2, qq = lane & 3;  // reduction: degree dd of the chunk, quarter qq of the 64 lanes
-    const int nblk = (cut + kBlk - 1) / kBlk;
+    const int nb = (hi - lo + kBlk - 1) / kBlk;
     StageRegs rg;
     int buf = 0;
-    if (nblk > 0) {
-        stage_load(rg, co, nullptr, 0, 0, cut, lane);
+    if (nb > 0) {
+        stage_load(rg, co, nullptr, lo, lo, hi, lane);
         stage_store(stg[0], rg, lane);
     }
     __syncthreads();
-    for (int b = 0; b < nblk; ++b) {
-        const int b0 = b * kBlk;
-        if (b + 1 < nblk) stage_load(rg, co, nullptr, b0 + kBlk, 0, cut, lane);
-        const Stage& S = stg[buf];
-        const int bend = min(kBlk, cut - b0);
+    for (int b = 0; b < nb; ++b) {
+        const int b0 = lo + b * kBlk;
+        if (b + 1 < nb) stage_load(rg, co, nullptr, b0 + kBlk, lo, hi, lane);
+        const Stage& St = stg[buf];
+        const int bend = min(kBlk, hi - b0);
         for (int c0 = 0; c0 < bend; c0 += kChunk) {
             const int nend = min(kChunk, bend - c0);
-#pragma unroll 8
+#pragma unroll 4
             for (int t = 0; t < nend; ++t) {
-                double v = 0.0;
+                if (!kMaps) {
+                    double v = 0.0;
 #pragma unroll
-                for (int q = 0; q < kPPT; ++q) v += pv[q];
-                red[t][lane] = v;
-                const d4 cf = S.co[c0 + t];
+                    for (int q = 0; q < kPPT; ++q) v += pv[0][q];
+                    red[t][lane] = v;
+                }
+                const d4 cf = St.co[c0 + t];
                 if (mode == 0) {
 #pragma unroll
-                    for (int q = 0; q < kPPT; ++q) {
-                        const double w = fma(xh[q], pv[q], xl[q] * pv[q]);
-                        const double p1 = fma(cf.x, w, fma(cf.y, pv[q], -cf.z * ev[q]));
-                        ev[q] = pv[q];
-                        pv[q] = p1;
-                    }
+                    for (int ch = 0; ch < NC; ++ch)
+#pragma unroll
+                        for (int q = 0; q < kPPT; ++q) {
+                            const double w = fma(xh[q], pv[ch][q], xl[q] * pv[ch][q]);
+                            const double p1 = fma(cf.x, w, fma(cf.y, pv[ch][q], -cf.z * ev[ch][q]));
+                            ev[ch][q] = pv[ch][q];
+                            pv[ch][q] = p1;
+                        }
                 } else {
 #pragma unroll
-                    for (int q = 0; q < kPPT; ++q) {
-                        const double w = fma(xh[q], pv[q], xl[q] * pv[q]);
-                        const double e1 = fma(cf.x, w, cf.y * ev[q]);
-                        pv[q] = fma(pv[q], cf.z, e1);
-                        ev[q] = e1;
-                    }
+                    for (int ch = 0; ch < NC; ++ch)
+#pragma unroll
+                        for (int q = 0; q < kPPT; ++q) {
+                            const double w = fma(xh[q], pv[ch][q], xl[q] * pv[ch][q]);
+                            const double e1 = fma(cf.x, w, cf.y * ev[ch][q]);
+                            pv[ch][q] = fma(pv[ch][q], cf.z, e1);
+                            ev[ch][q] = e1;
+                        }
                 }
             }
-            __syncthreads();
-            if (dd < nend) {
-                double sum = 0.0;
+            if (!kMaps) {
+                __syncthreads();
+                if (dd < nend) {
+                    double sum = 0.0;
 #pragma unroll
-                for (int l = 0; l < 16; ++l) sum += red[dd][qq * 16 + l];
-                sum += __shfl_xor(sum, 1);
-                sum += __shfl_xor(sum, 2);
-                if (qq == 0) part[b0 + c0 + dd] = sum;
+                    for (int l = 0; l < 16; ++l) sum += red[dd][qq * 16 + l];
+                    sum += __shfl_xor(sum, 1);
+                    sum += __shfl_xor(sum, 2);
+                    if (qq == 0) part[b0 + c0 + dd] = sum;
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
-        if (b + 1 < nblk) stage_store(stg[buf ^ 1], rg, lane);
+        if (b + 1 < nb) stage_store(stg[buf ^ 1], rg, lane);
         __syncthreads();
         buf ^= 1;
     }
-}
-
-cjt_status launch_rec_inv(const EngineArgs& a)
-{
-    if (a.count <= 0 || a.max_tasks <= 0) return CJT_OK;
-    dim3 grid(a.count, a.max_tasks);
-    hipLaunchKernelGGL(k_rec_inv, grid, dim3(64), 0, a.stream, a.d_desc);
-    CJT_HIP_TRY(hipGetLastError());
-    return CJT_OK;
-}
-
-// out[n] = s_n (out[n] + sum over tasks t with cut_t > n of part_t[n]); tasks
-// are sorted by decreasing cut, so they form a prefix.
-__global__ void __launch_bounds__(256) k_rec_inv_reduce(const ExecDesc* __restrict__ descs)
-{
-    const ExecDesc& d = descs[blockIdx.y];
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n > d.N) return;
-    double acc = 0.0;
-    cptr<RecTask> tasks = as_const(d.tasks);
-    for (int t = 0; t < d.ntasks; ++t) {
-        const int cut = tasks[t].cut;
-        if (cut <= n) break;
-        acc += d.part[tasks[t].off + n];
+    if (kMaps) {
+#pragma unroll
+        for (int q = 0; q < kPPT; ++q) {
+            const int idx = lane + 64 * q;
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch) {
+                rec[(2 * ch) * R + idx] = pv[ch][q];
+                rec[(2 * ch + 1) * R + idx] = ev[ch][q];
+            }
+        }
     }
-    d.out[n] = d.s[n] * (d.out[n] + acc);
 }
 
-cjt_status launch_rec_inv_reduce(const EngineArgs& a, int64_t maxN)
+// Item (desc, task, nseg, first slot): starting state of every segment,
+// (g_j, 0) at degree 0, then each segment's linear map (records 0..3).
+__global__ void __launch_bounds__(64) k_rec_inv_init(const ExecDesc* __restrict__ descs,
+                                                     const Item* __restrict__ items)
 {
-    if (a.count <= 0) return CJT_OK;
-    dim3 grid((unsigned)((maxN + 1 + 255) / 256), a.count);
-    hipLaunchKernelGGL(k_rec_inv_reduce, grid, dim3(256), 0, a.stream, a.d_desc);
+    const Item it = items[blockIdx.x];
+    const ExecDesc& d = descs[it.desc];
+    const TaskView tk = task_of(d, it.a);
+    const int nseg = it.b;
+    constexpr int R = 64 * kPPT;
+    for (int q = 0; q < kPPT; ++q) {
+        const int idx = threadIdx.x + 64 * q;
+        double x = idx < tk.np ? d.p[tk.p0 + idx] : 0.0, y = 0.0;
+        for (int s = 0; s < nseg; ++s) {
+            double* rec = d.seg + (int64_t)(it.c + s) * kRec + idx;
+            rec[4 * R] = x;
+            rec[5 * R] = y;
+            if (s + 1 < nseg) {
+                const double nx = fma(rec[0], x, rec[2 * R] * y);
+                const double ny = fma(rec[R], x, rec[3 * R] * y);
+                x = nx;
+                y = ny;
+            }
+        }
+    }
+}
+
+// out[n] = s_n (Hahn part + sum over tasks t with cut_t > n of part_t[n]).
+// Item (desc, tile of 32 degrees); 8 groups of 32 lanes split the tasks
+// (t = group mod 8) and are added in a fixed order.  Tasks are sorted by
+// decreasing cut, so the contributing ones form a prefix.
+__global__ void __launch_bounds__(256) k_rec_inv_reduce(const ExecDesc* __restrict__ descs,
+                                                        const Item* __restrict__ items)
+{
+    __shared__ double red[8][33];
+    const Item it = items[blockIdx.x];
+    const ExecDesc& d = descs[it.desc];
+    const int dn = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int64_t n = (int64_t)it.b * 32 + dn;
+    int lo = 0, hi = d.ntasks;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (d.tasks[mid].cut > n) lo = mid + 1;
+        else hi = mid;
+    }
+    const int T = lo;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int t = grp; t < T; t += 8) acc += d.part[d.tasks[t].off + n];
+    red[grp][dn] = acc;
+    __syncthreads();
+    if (grp == 0 && n <= d.N) {
+        double tot = 0.0;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) tot += red[g][dn];
+        const double base = d.nblk > 0 ? d.out[n] : 0.0;
+        d.out[n] = d.s[n] * (base + tot);
+    }
+}
+
+// ------------------------------------------------------------------ host side
+
+int32_t rec_segment_length(const Program& pr, const std::vector<const RecTask*>& tasks)
+{
+    if (const char* e = getenv("CJT_REC_SEGMENT")) {
+        const int v = atoi(e);
+        if (v > 0) return std::max(kBlk, (v + kBlk - 1) / kBlk * kBlk);
+    }
+    // total chain steps; no chain should be much longer than an even share
+    // of them over ~1024 concurrent waves
+    double W = 0.0;
+    for (size_t i = 0; i < pr.descs.size(); ++i)
+        for (int t = 0; t < pr.descs[i].ntasks; ++t) W += (double)tasks[i][t].cut;
+    const double S = std::max(1024.0, std::ceil(W / 1024.0));
+    const int Si = (int)std::min(S, 1.0e9);
+    return (Si + kBlk - 1) / kBlk * kBlk;
+}
+
+int64_t rec_seg_doubles(const ExecDesc& d, const RecTask* tasks, int32_t S)
+{
+    int64_t slots = 0;
+    for (int t = 0; t < d.ntasks; ++t) {
+        const int ns = seg_count(tasks[t].cut, S);
+        if (ns > 1) slots += ns;
+    }
+    return slots * kRec;
+}
+
+namespace {
+
+Launch rec_launch(Kind k, int stream, int nth, int32_t S, const char* name, double flops, double bytes)
+{
+    Launch L;
+    L.kind = k;
+    L.stream = stream;
+    L.nth = nth;
+    L.seg = S;
+    L.name = name;
+    L.flops = flops;
+    L.bytes = bytes;
+    return L;
+}
+
+void push(Program& pr, Launch L, const std::vector<Item>& items)
+{
+    if (items.empty()) return;
+    L.item_off = (int64_t)pr.items.size();
+    L.nitems = (int64_t)items.size();
+    pr.items.insert(pr.items.end(), items.begin(), items.end());
+    pr.launches.push_back(L);
+}
+
+}  // namespace
+
+void add_rec_fwd(Program& pr, const std::vector<const RecTask*>& tasks, int32_t S, int stream, double flops,
+                 double bytes)
+{
+    std::vector<Item> whole, segs, comb;
+    for (size_t i = 0; i < pr.descs.size(); ++i) {
+        int slot = 0;
+        for (int t = 0; t < pr.descs[i].ntasks; ++t) {
+            const int ns = seg_count(tasks[i][t].cut, S);
+            if (tasks[i][t].cut <= 0) continue;
+            if (ns == 1) {
+                whole.push_back(Item{(int32_t)i, t, 0, -1});
+            } else {
+                for (int s = 0; s < ns; ++s) segs.push_back(Item{(int32_t)i, t, s, slot + s});
+                comb.push_back(Item{(int32_t)i, t, ns, slot});
+                slot += ns;
+            }
+        }
+    }
+    push(pr, rec_launch(Kind::RecFwdSeg, stream, 64, S, "rec_forward", flops * 0.5, bytes * 0.5), segs);
+    push(pr, rec_launch(Kind::RecFwd, stream, 64, S, "rec_forward", segs.empty() ? flops : flops * 0.5,
+                        segs.empty() ? bytes : bytes * 0.5),
+         whole);
+    push(pr, rec_launch(Kind::RecFwdCombine, stream, 64, S, "rec_forward_combine", 0.0, 0.0), comb);
+}
+
+void add_rec_inv(Program& pr, const std::vector<const RecTask*>& tasks, int32_t S, int stream, double flops,
+                 double bytes)
+{
+    std::vector<Item> maps, init, all;
+    for (size_t i = 0; i < pr.descs.size(); ++i) {
+        int slot = 0;
+        for (int t = 0; t < pr.descs[i].ntasks; ++t) {
+            if (tasks[i][t].cut <= 0) continue;
+            const int ns = seg_count(tasks[i][t].cut, S);
+            if (ns == 1) {
+                all.push_back(Item{(int32_t)i, t, 0, -1});
+            } else {
+                for (int s = 0; s < ns; ++s) {
+                    if (s + 1 < ns) maps.push_back(Item{(int32_t)i, t, s, slot + s});
+                    all.push_back(Item{(int32_t)i, t, s, slot + s});
+                }
+                init.push_back(Item{(int32_t)i, t, ns, slot});
+                slot += ns;
+            }
+        }
+    }
+    push(pr, rec_launch(Kind::RecInvMaps, stream, 64, S, "rec_inverse_maps", 0.0, 0.0), maps);
+    push(pr, rec_launch(Kind::RecInvInit, stream, 64, S, "rec_inverse_init", 0.0, 0.0), init);
+    push(pr, rec_launch(Kind::RecInv, stream, 64, S, "rec_inverse", flops, bytes), all);
+}
+
+void add_rec_inv_reduce(Program& pr, int stream, double bytes)
+{
+    std::vector<Item> items;
+    for (size_t i = 0; i < pr.descs.size(); ++i)
+        for (int64_t t = 0; t < (pr.descs[i].N + 1 + 31) / 32; ++t) items.push_back(Item{(int32_t)i, 0, (int32_t)t, 0});
+    push(pr, rec_launch(Kind::RecInvReduce, stream, 256, 0, "rec_inverse_reduce", 0.0, bytes), items);
+}
+
+cjt_status launch_rec(const Launch& L, const ExecDesc* dd, const Item* it, hipStream_t s)
+{
+    if (L.nitems <= 0) return CJT_OK;
+    ProfScope ps(L.name, L.flops, L.bytes, s);
+    const dim3 grid((unsigned)L.nitems), block(L.nth);
+    switch (L.kind) {
+    case Kind::RecFwd: hipLaunchKernelGGL(k_rec_fwd<false>, grid, block, 0, s, dd, it, L.seg); break;
+    case Kind::RecFwdSeg: hipLaunchKernelGGL(k_rec_fwd<true>, grid, block, 0, s, dd, it, L.seg); break;
+    case Kind::RecFwdCombine: hipLaunchKernelGGL(k_rec_fwd_combine, grid, block, 0, s, dd, it); break;
+    case Kind::RecInvMaps: hipLaunchKernelGGL(k_rec_inv<true>, grid, block, 0, s, dd, it, L.seg); break;
+    case Kind::RecInvInit: hipLaunchKernelGGL(k_rec_inv_init, grid, block, 0, s, dd, it); break;
+    case Kind::RecInv: hipLaunchKernelGGL(k_rec_inv<false>, grid, block, 0, s, dd, it, L.seg); break;
+    case Kind::RecInvReduce: hipLaunchKernelGGL(k_rec_inv_reduce, grid, block, 0, s, dd, it); break;
+    default: return fail(CJT_EINVAL, "not a recurrence launch");
+    }
     CJT_HIP_TRY(hipGetLastError());
     return CJT_OK;
 }

@@ -154,6 +154,23 @@ def test_any_length_exact_case(lib, oracle_mod):
     assert ef <= tol(N) and eg <= tol(N)
 
 
+@pytest.mark.parametrize("N,seg", [(4096, 256), (3000, 128), (16384, 1024), (2049, 384)])
+def test_segmented_recurrences(lib, oracle_mod, monkeypatch, N, seg):
+    """Recurrence tasks longer than two segments are split in degree and their
+    affine maps chained; forced short segments must give the oracle's result."""
+    monkeypatch.setenv("CJT_REC_SEGMENT", str(seg))
+    rng = np.random.default_rng(500 + N)
+    a, b = float(rng.uniform(-0.5, 0.5)), float(rng.uniform(-0.5, 0.5))
+    c = inputs.decaying_coeffs(rng, N, 1.0)
+    f_ref, g_ref = oracle_pair(oracle_mod, c, a, b)
+    for M in (0, 2):  # automatic M, and a plan that is recurrence everywhere
+        f, plan = run_fwd(lib, c, a, b, M=M)
+        g, _ = run_inv(lib, c, a, b, M=M)
+        ef, eg = rel2(f, f_ref), rel2(g, g_ref)
+        print(f"N={N} seg={seg} M={plan.info.M} fwd {ef:.2e} inv {eg:.2e}")
+        assert ef <= tol(N) and eg <= tol(N)
+
+
 def test_fp32_bulk_error_reported(lib, oracle_mod):
     """FP32 Hahn-block FFTs: no bound in the paper (parity unpinned); the error is
     measured and must stay at single-precision level."""
