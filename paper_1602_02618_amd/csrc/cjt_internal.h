@@ -110,8 +110,70 @@ __device__ __forceinline__ cptr<T> as_const(const T* p)
 // not bind to address-space-qualified references).
 __device__ __forceinline__ d4 ld(cptr<d4> p) { return d4{p->x, p->y, p->z, p->w}; }
 
+// Global-memory accessors.  The device pointers of a descriptor are read
+// from memory, so the compiler cannot tell that they point to global memory
+// and would use flat instructions: 64-bit per-lane addresses, and a shared
+// wait counter with LDS, so every LDS wait would also wait for the loads in
+// flight.  Going through address space 1 gives global loads/stores with a
+// scalar base and a 32-bit lane offset.
+template <typename T>
+using gptr = T __attribute__((address_space(1)))*;
+
+template <typename T>
+struct vec2_of;
+template <>
+struct vec2_of<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct vec2_of<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+// two consecutive doubles at an address that is only 8-byte aligned
+typedef double dpair8 __attribute__((ext_vector_type(2), aligned(8)));
+
+__device__ __forceinline__ double ldg(const double* p) { return *(gptr<const double>)p; }
+__device__ __forceinline__ float ldg(const float* p) { return *(gptr<const float>)p; }
+__device__ __forceinline__ int32_t ldg(const int32_t* p) { return *(gptr<const int32_t>)p; }
+__device__ __forceinline__ int64_t ldg(const int64_t* p) { return *(gptr<const int64_t>)p; }
+__device__ __forceinline__ void stg(double* p, double v) { *(gptr<double>)p = v; }
+template <typename T>
+__device__ __forceinline__ cx<T> ldg(const cx<T>* p)
+{
+    typedef typename vec2_of<T>::type V;
+    const V v = *(gptr<const V>)p;
+    return {v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void stg(cx<T>* p, cx<T> a)
+{
+    typedef typename vec2_of<T>::type V;
+    V v;
+    v.x = a.re;
+    v.y = a.im;
+    *(gptr<V>)p = v;
+}
+__device__ __forceinline__ dpair8 ldg_pair(const double* p) { return *(gptr<const dpair8>)p; }
+// one recurrence coefficient record (32 bytes, 32-byte aligned)
+__device__ __forceinline__ d4 ldg(const d4* p)
+{
+    typedef double V __attribute__((ext_vector_type(4)));
+    const V v = *(gptr<const V>)p;
+    return d4{v.x, v.y, v.z, v.w};
+}
+
 // Wave-uniform copy of an int (the value must already be equal in all lanes).
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Workgroup b of a launch runs on XCD b mod 8 (each XCD has its own L2).
+// Launches whose neighbouring items share inputs map workgroups to items so
+// that every XCD takes one contiguous range of the item list.
+__device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t nb)
+{
+    constexpr int64_t X = 8;
+    const int64_t q = nb / X, r = nb % X, x = b % X, i = b / X;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
 
 constexpr int64_t kSingleMax = 4096;
 // Largest degree: the inverse's length-2N transform must fit the two-pass
@@ -160,6 +222,9 @@ enum class Kind : int32_t {
     BsCol1, BsRow1,  // chirp-z, first transform (two passes)
     BsCol2, BsRow2,  // chirp-z, second transform (two passes)
     BsUntangle,      // chirp-z untangling + sink
+    FftJobs,         // one job of a power-of-two single-workgroup transform, sink parts per job
+    BsJobs,          // one job of a chirp-z single-workgroup transform, sink parts per job
+    JobReduce,       // sum of the per-job sink parts
     RecFwd,          // forward recurrence over the whole degree range of a task
     RecFwdSeg,       // forward recurrence over one degree segment of a long task (affine map)
     RecFwdCombine,   // forward: chain the affine maps of a split task's segments
@@ -196,7 +261,10 @@ struct Program {
 // instance, for the timing labels.
 cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sink, bool fp32, int stream,
                    const char* name_cols, const char* name_rows, const std::vector<double>& flops,
-                   const std::vector<double>& bytes);
+                   const std::vector<double>& bytes, bool job_parallel = false);
+// Intermediate bytes one instance needs for a pass of `jobs` jobs over the
+// length of geometry g (0: none), in the mode add_fft will choose.
+size_t fft_tmp_bytes(const FftGeom& g, int64_t jobs, bool fp32, bool job_parallel);
 // Recurrence launches over all instances; the segment length `seg` splits
 // tasks whose degree range exceeds 2*seg.  Returns the segment-record
 // doubles each instance needs (rec_seg_doubles) before the seg pointers are set.

@@ -18,6 +18,11 @@ namespace {
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Calls with at most this many instances run the Hahn jobs of short lengths
+// one workgroup each (latency); larger calls loop over the jobs inside one
+// workgroup per instance (no intermediate traffic).
+constexpr size_t kJobParallelMax = 64;
+
 // Algorithmic work of one transform's kernels (the counting of cjt_profile_enable).
 struct Work {
     double rec_flops = 0, asy_flops = 0, bnd_flops = 0;
@@ -114,6 +119,8 @@ cjt_status build_program(const std::vector<const Plan*>& plans, const std::vecto
         red_b += 16.0 * (double)(P.N + 1);
     }
     const int32_t S = rec_segment_length(pr, tasks);
+    // few instances: spread the Hahn jobs of single-workgroup lengths over workgroups
+    const bool job_parallel = n <= kJobParallelMax;
 
     // workspace: persistent p, p2, part, seg for all instances, then one
     // region of FFT intermediates reused by consecutive chunks of instances
@@ -143,8 +150,8 @@ cjt_status build_program(const std::vector<const Plan*>& plans, const std::vecto
             off += a256(sizeof(double) * (size_t)segd);
         }
         const int64_t jobs = (int64_t)d.nblk * d.M;
-        size_t t = (size_t)std::max<int64_t>(jobs, 1) * fft_job_bytes(d.G, fp32);
-        t = std::max(t, fft_job_bytes(d.G, false));  // boundary transforms (FP64)
+        size_t t = fft_tmp_bytes(d.geob, jobs, fp32, job_parallel);   // Hahn blocks
+        t = std::max(t, fft_tmp_bytes(d.geo, 1, false, job_parallel));  // boundary transform (FP64)
         tmp_need[i] = a256(t);
     }
     const size_t persist = off;
@@ -185,7 +192,7 @@ cjt_status build_program(const std::vector<const Plan*>& plans, const std::vecto
         add_rec_fwd(pr, tasks, S, 1, rec_f, rec_b);
         for (auto& c : chunks)
             if ((s = add_fft(pr, c, Src::FwdAsy, Sink::FwdAsy, fp32, 0, fp32 ? "hahn_fwd_cols_fp32" : "hahn_fwd_cols",
-                             fp32 ? "hahn_fwd_rows_fp32" : "hahn_fwd_rows", asy_f, asy_b)) != CJT_OK)
+                             fp32 ? "hahn_fwd_rows_fp32" : "hahn_fwd_rows", asy_f, asy_b, job_parallel)) != CJT_OK)
                 return s;
         mark(Kind::Join);
         for (auto& c : chunks)
@@ -201,10 +208,28 @@ cjt_status build_program(const std::vector<const Plan*>& plans, const std::vecto
         add_rec_inv(pr, tasks, S, 1, rec_f, rec_b);
         for (auto& c : chunks)
             if ((s = add_fft(pr, c, Src::InvAsy, Sink::InvAsy, fp32, 0, fp32 ? "hahn_inv_cols_fp32" : "hahn_inv_cols",
-                             fp32 ? "hahn_inv_rows_fp32" : "hahn_inv_rows", asy_f, asy_b)) != CJT_OK)
+                             fp32 ? "hahn_inv_rows_fp32" : "hahn_inv_rows", asy_f, asy_b, job_parallel)) != CJT_OK)
                 return s;
         mark(Kind::Join);
         add_rec_inv_reduce(pr, 0, red_b);
+    }
+    // every launch that keeps intermediates must find them: a missing buffer
+    // is an error here rather than a null pointer on the device
+    for (const Launch& L : pr.launches) {
+        switch (L.kind) {
+        case Kind::FftPass1: case Kind::FftPass2: case Kind::BsCol1: case Kind::BsRow1: case Kind::BsCol2:
+        case Kind::BsRow2: case Kind::BsUntangle: case Kind::FftJobs: case Kind::BsJobs: case Kind::JobReduce:
+            for (int64_t q = 0; q < L.nitems; ++q)
+                if (b.offs[pr.items[L.item_off + q].desc].tmp == SIZE_MAX)
+                    return fail(CJT_EINVAL, "internal: FFT intermediates missing for a two-pass or job-parallel launch");
+            break;
+        case Kind::RecFwdSeg: case Kind::RecFwdCombine: case Kind::RecInvMaps: case Kind::RecInvInit:
+            for (int64_t q = 0; q < L.nitems; ++q)
+                if (b.offs[pr.items[L.item_off + q].desc].seg == SIZE_MAX)
+                    return fail(CJT_EINVAL, "internal: segment records missing for a split recurrence");
+            break;
+        default: break;
+        }
     }
     return CJT_OK;
 }
@@ -253,6 +278,9 @@ cjt_status run_program(const Program& pr, const ExecDesc* d_desc, const Item* d_
         case Kind::BsCol2:
         case Kind::BsRow2:
         case Kind::BsUntangle:
+        case Kind::FftJobs:
+        case Kind::BsJobs:
+        case Kind::JobReduce:
             if ((s = launch_fft(L, d_desc, it, ls)) != CJT_OK) return s;
             break;
         default:

@@ -12,7 +12,8 @@
 // Twiddles come from a table tw[q] = exp(i pi q / L), q < 2L, of the transform
 // length L that this F-point transform is part of (F divides L); they are
 // computed once per length from the exact rational angle, so no angle is ever
-// formed by accumulation.
+// formed by accumulation.  All lengths are powers of two up to 2^24, so
+// indices and strides are 32-bit and divisions are shifts.
 #pragma once
 
 #include "cjt_internal.h"
@@ -138,7 +139,7 @@ __device__ __forceinline__ void dft(cx<T>* v)
 // twmul = 2L / (Ns R) maps the stage twiddle exp(2 pi i r k / (Ns R)) into tw.
 template <typename T, int R, int BPT>
 __device__ __forceinline__ void fft_stage(cx<T>* buf, int F, int Ns, int lt, int base, bool active,
-                                          const cx<T>* __restrict__ tw, int64_t twmul)
+                                          const cx<T>* __restrict__ tw, int twmul)
 {
     cx<T> v[BPT][R];
     const int FR = F / R;
@@ -159,7 +160,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int F, int Ns, int lt, int
             int k = j & (Ns - 1);
             if (Ns > 1) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[(int64_t)(r * k) * twmul]);
+                for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], ldg(tw + (r * k) * twmul));
             }
             dft<T, R>(v[q]);
             int idxD = (j - k) * R + k;
@@ -175,7 +176,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int F, int Ns, int lt, int
 // threads of the workgroup must call this.  L2x = 2L of the parent length.
 template <typename T>
 __device__ __forceinline__ void lds_fft(cx<T>* buf, int logF, int nfft, const cx<T>* __restrict__ tw,
-                                        int64_t L2x)
+                                        int L2x)
 {
     const int F = 1 << logF;
     if (logF == 0) {
@@ -192,7 +193,7 @@ __device__ __forceinline__ void lds_fft(cx<T>* buf, int logF, int nfft, const cx
     int rem = logF;
     while (rem > 0) {
         const int lr = rem >= 4 ? 4 : rem;
-        const int64_t twmul = L2x / ((int64_t)Ns << lr);
+        const int twmul = L2x >> (__builtin_ctz(Ns) + lr);
         if (lr == 4) {
             fft_stage<T, 16, 1>(buf, F, Ns, lt, base, active, tw, twmul);
         } else if (F >= 16) {
@@ -240,7 +241,7 @@ __device__ __forceinline__ int fft_out_index(int s, int lt, int logF)
 
 template <typename T, int R, int BPT>
 __device__ __forceinline__ void fft_reg_last(cx<T> (&v)[16], const cx<T>* buf, int F, int Ns, int lt,
-                                             const cx<T>* __restrict__ tw, int64_t twmul)
+                                             const cx<T>* __restrict__ tw, int twmul)
 {
     const int FR = F / R;
     const int stride = FR / BPT;
@@ -252,7 +253,7 @@ __device__ __forceinline__ void fft_reg_last(cx<T> (&v)[16], const cx<T>* buf, i
 #pragma unroll
         for (int r = 0; r < R; ++r) w[r] = buf[lds_pad(j + r * FR)];
 #pragma unroll
-        for (int r = 1; r < R; ++r) w[r] = cmul(w[r], tw[(int64_t)(r * k) * twmul]);
+        for (int r = 1; r < R; ++r) w[r] = cmul(w[r], ldg(tw + (r * k) * twmul));
         dft<T, R>(w);
 #pragma unroll
         for (int r = 0; r < R; ++r) v[q * R + r] = w[r];
@@ -263,7 +264,7 @@ __device__ __forceinline__ void fft_reg_last(cx<T> (&v)[16], const cx<T>* buf, i
 // marks threads that own a transform.
 template <typename T>
 __device__ __forceinline__ void fft_reg(cx<T> (&v)[16], cx<T>* buf, int logF, int lt, bool active,
-                                        const cx<T>* __restrict__ tw, int64_t L2x)
+                                        const cx<T>* __restrict__ tw, int L2x)
 {
     const int F = 1 << logF;
     const int nst = (logF + 3) >> 2;  // stages: radix 16 ..., last one radix 2^(logF - 4(nst-1))
@@ -278,11 +279,11 @@ __device__ __forceinline__ void fft_reg(cx<T> (&v)[16], cx<T>* buf, int logF, in
     int Ns = 16;
     for (int st = 1; st + 1 < nst; ++st) {
         // middle radix-16 stages through LDS
-        fft_stage<T, 16, 1>(buf, F, Ns, lt, 0, active, tw, L2x / ((int64_t)Ns << 4));
+        fft_stage<T, 16, 1>(buf, F, Ns, lt, 0, active, tw, L2x >> (__builtin_ctz(Ns) + 4));
         Ns <<= 4;
     }
     const int lr = logF - 4 * (nst - 1);
-    const int64_t twmul = L2x / ((int64_t)Ns << lr);
+    const int twmul = L2x >> (__builtin_ctz(Ns) + lr);
     if (active) {
         if (lr == 4) fft_reg_last<T, 16, 1>(v, buf, F, Ns, lt, tw, twmul);
         else if (lr == 3) fft_reg_last<T, 8, 2>(v, buf, F, Ns, lt, tw, twmul);

@@ -35,6 +35,8 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <set>
+#include <string>
 
 #include "cjt_internal.h"
 #include "fft_lds.h"
@@ -42,6 +44,11 @@
 namespace cjt {
 
 // ------------------------------------------------------------------ sources
+//
+// Indices inside one transform are 32-bit (lengths are at most 2^23); a
+// half-open range test lo <= n < hi is one unsigned compare.
+
+__device__ __forceinline__ bool in_range(int n, int lo, int hi) { return (unsigned)(n - lo) < (unsigned)(hi - lo); }
 
 template <Src S>
 struct Source;
@@ -50,57 +57,75 @@ template <>
 struct Source<Src::FwdAsy> {
     // job = k * M + m
     static constexpr bool kMulti = true;
-    __device__ static bool valid(const ExecDesc& d, int job) { return job < d.nblk * d.M; }
-    __device__ static cx<double> load(const ExecDesc& d, int job, int64_t t)
+    __device__ static cx<double> load(const ExecDesc& d, int job, int t)
     {
         const int k = job / d.M, m = job - k * d.M;
-        const int64_t lo = d.deg_lo[k], hi = d.deg_hi[k];
-        const int64_t n0 = 2 * t, n1 = n0 + 1;
+        const int lo = (int)d.deg_lo[k], hi = (int)d.deg_hi[k];
+        const int n0 = 2 * t, n1 = n0 + 1;
         const double* Cm = d.C + (int64_t)m * (d.N + 1);
-        double x0 = (n0 >= lo && n0 < hi) ? Cm[n0] * d.in[n0] : 0.0;
-        double x1 = (n1 >= lo && n1 < hi) ? Cm[n1] * d.in[n1] : 0.0;
-        return {x0, x1};
+        const bool a0 = in_range(n0, lo, hi), a1 = in_range(n1, lo, hi);
+        if (a0 && a1) {  // both degrees present (n1 <= N): one pair of loads each
+            const dpair8 c = ldg_pair(Cm + n0), x = ldg_pair(d.in + n0);
+            return {c.x * x.x, c.y * x.y};
+        }
+        return {a0 ? ldg(Cm + n0) * ldg(d.in + n0) : 0.0, a1 ? ldg(Cm + n1) * ldg(d.in + n1) : 0.0};
     }
 };
 
 template <>
 struct Source<Src::InvAsy> {
     static constexpr bool kMulti = true;
-    __device__ static bool valid(const ExecDesc& d, int job) { return job < d.nblk * d.M; }
     // a_j = u_m(theta_j) g_j, b_j = v_m(theta_j) g_j on the window (zero elsewhere);
     // r_0 = a_0, r_G = a_G, r_j = (a_j + b_j)/2 and r_{2G-j} = (a_j - b_j)/2 for 0 < j < G.
-    __device__ static double r(const ExecDesc& d, int k, const cx<double>* uvm, int64_t q)
+    __device__ static double r1(int G, double g, cx<double> uv, int j, bool mirror)
     {
-        const int64_t G = d.G;
-        int64_t j;
-        double sb;
-        if (q <= G) { j = q; sb = 1.0; }
-        else { j = 2 * G - q; sb = -1.0; }
-        if (j < d.win_lo[k] || j > d.win_hi[k]) return 0.0;
-        const double g = d.p[j];
-        const cx<double> uv = uvm[j];
         if (j == 0 || j == G) return uv.re * g;
-        return 0.5 * (uv.re * g + sb * uv.im * g);
+        return 0.5 * g * (mirror ? uv.re - uv.im : uv.re + uv.im);
     }
-    __device__ static cx<double> load(const ExecDesc& d, int job, int64_t t)
+    // (r_q, r_{q+1}) for even q.  q <= G - 1 reads points q, q+1; q >= G + 1
+    // reads 2G - q - 1, 2G - q (the mirror); q = G straddles the two halves.
+    __device__ static cx<double> load(const ExecDesc& d, int job, int t)
     {
         const int k = job / d.M, m = job - k * d.M;
+        const int lo = (int)d.win_lo[k], hi = (int)d.win_hi[k] + 1;
         const cx<double>* uvm = d.uv + (int64_t)m * (d.G + 1);
-        return {r(d, k, uvm, 2 * t), r(d, k, uvm, 2 * t + 1)};
+        const int G = (int)d.G;
+        const int q = 2 * t;
+        if (q + 1 <= G || q > G) {
+            const bool mirror = q > G;
+            const int j0 = mirror ? 2 * G - q : q;    // point of r_q
+            const int j1 = mirror ? j0 - 1 : j0 + 1;  // point of r_{q+1}
+            const int jl = mirror ? j1 : j0;          // lower of the two
+            const bool a0 = in_range(j0, lo, hi), a1 = in_range(j1, lo, hi);
+            if (!a0 && !a1) return {0.0, 0.0};
+            if (a0 && a1) {
+                const dpair8 g = ldg_pair(d.p + jl);
+                const cx<double> ua = ldg(uvm + jl), ub = ldg(uvm + jl + 1);
+                const double g0 = mirror ? g.y : g.x, g1 = mirror ? g.x : g.y;
+                const cx<double> u0 = mirror ? ub : ua, u1 = mirror ? ua : ub;
+                return {r1(G, g0, u0, j0, mirror), r1(G, g1, u1, j1, mirror)};
+            }
+            const int j = a0 ? j0 : j1;
+            const double v = r1(G, ldg(d.p + j), ldg(uvm + j), j, mirror);
+            return a0 ? cx<double>{v, 0.0} : cx<double>{0.0, v};
+        }
+        // q = G (G even): r_G from point G, r_{G+1} from point G - 1 (mirrored)
+        const bool a0 = in_range(G, lo, hi), a1 = in_range(G - 1, lo, hi);
+        return {a0 ? r1(G, ldg(d.p + G), ldg(uvm + G), G, false) : 0.0,
+                a1 ? r1(G, ldg(d.p + G - 1), ldg(uvm + G - 1), G - 1, true) : 0.0};
     }
 };
 
 template <>
 struct Source<Src::FwdFinal> {
     static constexpr bool kMulti = false;
-    __device__ static bool valid(const ExecDesc&, int job) { return job == 0; }
     // p = recurrence part + Hahn-block part (the latter only if the plan has blocks)
-    __device__ static double pv(const ExecDesc& d, int64_t j) { return d.nblk > 0 ? d.p[j] + d.p2[j] : d.p[j]; }
-    __device__ static cx<double> load(const ExecDesc& d, int, int64_t t)
+    __device__ static double pv(const ExecDesc& d, int j) { return d.nblk > 0 ? ldg(d.p + j) + ldg(d.p2 + j) : ldg(d.p + j); }
+    __device__ static cx<double> load(const ExecDesc& d, int, int t)
     {
-        const int64_t N = d.N, j0 = 2 * t, j1 = j0 + 1;
-        double x0 = j0 <= N ? pv(d, j0) * ((j0 == 0 || j0 == N) ? 0.5 : 1.0) : 0.0;
-        double x1 = j1 <= N ? pv(d, j1) * ((j1 == N) ? 0.5 : 1.0) : 0.0;
+        const int N = (int)d.N, j0 = 2 * t, j1 = j0 + 1;
+        const double x0 = j0 <= N ? pv(d, j0) * ((j0 == 0 || j0 == N) ? 0.5 : 1.0) : 0.0;
+        const double x1 = j1 <= N ? pv(d, j1) * ((j1 == N) ? 0.5 : 1.0) : 0.0;
         return {x0, x1};
     }
 };
@@ -108,11 +133,10 @@ struct Source<Src::FwdFinal> {
 template <>
 struct Source<Src::InvInit> {
     static constexpr bool kMulti = false;
-    __device__ static bool valid(const ExecDesc&, int job) { return job == 0; }
-    __device__ static cx<double> load(const ExecDesc& d, int, int64_t t)
+    __device__ static cx<double> load(const ExecDesc& d, int, int t)
     {
-        const int64_t N = d.N, k0 = 2 * t, k1 = k0 + 1;
-        return {k0 <= N ? d.in[k0] : 0.0, k1 <= N ? d.in[k1] : 0.0};
+        const int N = (int)d.N, k0 = 2 * t, k1 = k0 + 1;
+        return {k0 <= N ? ldg(d.in + k0) : 0.0, k1 <= N ? ldg(d.in + k1) : 0.0};
     }
 };
 
@@ -120,12 +144,11 @@ template <>
 struct Source<Src::Moments> {
     static constexpr bool kMulti = false;
     // in = mu_0..mu_G, halved at both ends
-    __device__ static bool valid(const ExecDesc&, int job) { return job == 0; }
-    __device__ static cx<double> load(const ExecDesc& d, int, int64_t t)
+    __device__ static cx<double> load(const ExecDesc& d, int, int t)
     {
-        const int64_t G = d.G, k0 = 2 * t, k1 = k0 + 1;
-        double x0 = k0 <= G ? d.in[k0] * ((k0 == 0 || k0 == G) ? 0.5 : 1.0) : 0.0;
-        double x1 = k1 <= G ? d.in[k1] * ((k1 == G) ? 0.5 : 1.0) : 0.0;
+        const int G = (int)d.G, k0 = 2 * t, k1 = k0 + 1;
+        const double x0 = k0 <= G ? ldg(d.in + k0) * ((k0 == 0 || k0 == G) ? 0.5 : 1.0) : 0.0;
+        const double x1 = k1 <= G ? ldg(d.in + k1) * ((k1 == G) ? 0.5 : 1.0) : 0.0;
         return {x0, x1};
     }
 };
@@ -142,60 +165,60 @@ struct Target;
 
 template <>
 struct Target<Sink::FwdAsy> {
-    __device__ static double contrib(const ExecDesc& d, int job, int64_t i, cx<double> X)
+    __device__ static double contrib(const ExecDesc& d, int job, int i, cx<double> X)
     {
         const int k = job / d.M, m = job - k * d.M;
-        if (i < d.win_lo[k] || i > d.win_hi[k]) return 0.0;
-        const cx<double> uv = d.uv[(int64_t)m * (d.G + 1) + i];
+        if (!in_range(i, (int)d.win_lo[k], (int)d.win_hi[k] + 1)) return 0.0;
+        const cx<double> uv = ldg(d.uv + (int64_t)m * (d.G + 1) + i);
         return fma(uv.re, X.re, uv.im * X.im);
     }
     // every point is written (zero outside the windows); the final DCT-I adds
     // the recurrence part
-    __device__ static void finish(const ExecDesc& d, int64_t i, double v) { d.p2[i] = v; }
+    __device__ static void finish(const ExecDesc& d, int i, double v) { stg(d.p2 + i, v); }
 };
 
 template <>
 struct Target<Sink::InvAsy> {
-    __device__ static double contrib(const ExecDesc& d, int job, int64_t n, cx<double> X)
+    __device__ static double contrib(const ExecDesc& d, int job, int n, cx<double> X)
     {
         const int k = job / d.M, m = job - k * d.M;
-        if (n < d.deg_lo[k] || n >= d.deg_hi[k]) return 0.0;
-        return d.C[(int64_t)m * (d.N + 1) + n] * (X.re + X.im);
+        if (!in_range(n, (int)d.deg_lo[k], (int)d.deg_hi[k])) return 0.0;
+        return ldg(d.C + (int64_t)m * (d.N + 1) + n) * (X.re + X.im);
     }
     // Every degree 0..N is written (zero outside the blocks); the recurrence
     // reduction adds its part and applies 1/A_n afterwards.
-    __device__ static void finish(const ExecDesc& d, int64_t n, double v)
+    __device__ static void finish(const ExecDesc& d, int n, double v)
     {
-        if (n <= d.N) d.out[n] = v;
+        if (n <= d.N) stg(d.out + n, v);
     }
 };
 
 template <>
 struct Target<Sink::FwdFinal> {
-    __device__ static double contrib(const ExecDesc&, int, int64_t, cx<double> X) { return X.re; }
-    __device__ static void finish(const ExecDesc& d, int64_t k, double v)
+    __device__ static double contrib(const ExecDesc&, int, int, cx<double> X) { return X.re; }
+    __device__ static void finish(const ExecDesc& d, int k, double v)
     {
-        const int64_t N = d.N;
+        const int N = (int)d.N;
         const double sc = (k == 0 || k == N) ? 1.0 / (double)N : 2.0 / (double)N;
-        d.out[k] = sc * v;
+        stg(d.out + k, sc * v);
     }
 };
 
 template <>
 struct Target<Sink::InvInit> {
-    __device__ static double contrib(const ExecDesc&, int, int64_t, cx<double> X) { return X.re; }
-    __device__ static void finish(const ExecDesc& d, int64_t j, double v) { d.p[j] = d.w[j] * v; }
+    __device__ static double contrib(const ExecDesc&, int, int, cx<double> X) { return X.re; }
+    __device__ static void finish(const ExecDesc& d, int j, double v) { stg(d.p + j, ldg(d.w + j) * v); }
 };
 
 template <>
 struct Target<Sink::Weights> {
-    __device__ static double contrib(const ExecDesc&, int, int64_t, cx<double> X) { return X.re; }
+    __device__ static double contrib(const ExecDesc&, int, int, cx<double> X) { return X.re; }
     // w_j = (1 - (d_j0 + d_jG)/2) / (G/2) Re X_j
-    __device__ static void finish(const ExecDesc& d, int64_t j, double v)
+    __device__ static void finish(const ExecDesc& d, int j, double v)
     {
-        const int64_t G = d.G;
+        const int G = (int)d.G;
         const double sc = ((j == 0 || j == G) ? 0.5 : 1.0) / (0.5 * (double)G);
-        d.out[j] = sc * v;
+        stg(d.out + j, sc * v);
     }
 };
 
@@ -237,7 +260,7 @@ __device__ __forceinline__ const FftGeom& geom_of<float>(const ExecDesc& d) { re
 
 // X_s and X_{L-s} of the real-input DFT from the complex FFT Z (any L; s <= L/2).
 template <typename T, typename ZAt>
-__device__ __forceinline__ void untangle_at(ZAt Z, int64_t L, int64_t s, cx<T> w, cx<double>& xa, cx<double>& xb)
+__device__ __forceinline__ void untangle_at(ZAt Z, int L, int s, cx<T> w, cx<double>& xa, cx<double>& xb)
 {
     if (s == 0) {
         const cx<T> z = Z(0);
@@ -257,48 +280,47 @@ __device__ __forceinline__ void untangle_at(ZAt Z, int64_t L, int64_t s, cx<T> w
 // of column c holds n1 = lt + r F1/16.  Output k1 of column n2 is multiplied by
 // e^{2 pi i n2 k1 / F}.  load(t) gives input t = n1 F2 + n2; store(k1 F2 + n2, v).
 template <typename T, typename LoadF, typename StoreF>
-__device__ __forceinline__ void col_pass(cx<T>* lds, int lg1, int lg2, const cx<T>* __restrict__ tw, int64_t tile,
+__device__ __forceinline__ void col_pass(cx<T>* lds, int lg1, int lg2, const cx<T>* __restrict__ tw, int tile,
                                          LoadF load, StoreF store)
 {
     const int F1 = 1 << lg1;
-    const int64_t F2 = (int64_t)1 << lg2, F = F2 << lg1;
-    const int TC = F1 >= 2048 ? 1 : 2048 / F1;
+    const int F = 1 << (lg1 + lg2);
+    const int ltc = lg1 >= 11 ? 0 : 11 - lg1;  // TC = 2048 / F1 columns
     const int tid = threadIdx.x;
-    const int c = tid % TC, lt = tid / TC;
-    const int64_t col = tile * TC + c;
+    const int c = tid & ((1 << ltc) - 1), lt = tid >> ltc;
+    const int col = (tile << ltc) + c;
     const int step = F1 >> 4;
     cx<T> v[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = load((int64_t)(lt + r * step) * F2 + col);
+    for (int r = 0; r < 16; ++r) v[r] = load(((lt + r * step) << lg2) + col);
     fft_reg<T>(v, lds + c * slice_stride(F1), lg1, lt, true, tw, 2 * F);
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-        const int64_t k1 = fft_out_index(s, lt, lg1);
-        const int64_t q = (2 * col * k1) & (2 * F - 1);  // e^{2 pi i n2 k1 / F} = tw[2 n2 k1 mod 2F]
-        store(k1 * F2 + col, cmul(v[s], tw[q]));
+        const int k1 = fft_out_index(s, lt, lg1);
+        const int q = (2 * col * k1) & (2 * F - 1);  // e^{2 pi i n2 k1 / F} = tw[2 n2 k1 mod 2F]
+        store((k1 << lg2) + col, cmul(v[s], ldg(tw + q)));
     }
 }
 
 // Row pass: TR = max(1, 2048 / F2) rows k1 per workgroup (F2/16 threads each);
 // load(k1 F2 + n2), store(k1 + F1 k2, X) in natural frequency order.
 template <typename T, typename LoadF, typename StoreF>
-__device__ __forceinline__ void row_pass(cx<T>* lds, int lg1, int lg2, const cx<T>* __restrict__ tw, int64_t tile,
+__device__ __forceinline__ void row_pass(cx<T>* lds, int lg1, int lg2, const cx<T>* __restrict__ tw, int tile,
                                          LoadF load, StoreF store)
 {
-    const int64_t F1 = (int64_t)1 << lg1;
     const int F2 = 1 << lg2;
-    const int64_t F = F1 << lg2;
-    const int TR = F2 >= 2048 ? 1 : 2048 / F2;
-    const int tpr = F2 >> 4;
+    const int F = 1 << (lg1 + lg2);
+    const int ltr = lg2 >= 11 ? 0 : 11 - lg2;  // TR = 2048 / F2 rows
+    const int ltp = lg2 - 4;                    // threads per row: F2 / 16
     const int tid = threadIdx.x;
-    const int rr = tid / tpr, lt = tid - rr * tpr;
-    const int64_t k1 = tile * TR + rr;
+    const int rr = tid >> ltp, lt = tid & ((1 << ltp) - 1);
+    const int k1 = (tile << ltr) + rr;
     cx<T> v[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = load(k1 * F2 + lt + r * tpr);
+    for (int r = 0; r < 16; ++r) v[r] = load((k1 << lg2) + lt + (r << ltp));
     fft_reg<T>(v, lds + rr * slice_stride(F2), lg2, lt, true, tw, 2 * F);
 #pragma unroll
-    for (int s = 0; s < 16; ++s) store(k1 + F1 * fft_out_index(s, lt, lg2), v[s]);
+    for (int s = 0; s < 16; ++s) store(k1 + (fft_out_index(s, lt, lg2) << lg1), v[s]);
 }
 
 // ------------------------------------------------------------------ power of two, one workgroup
@@ -329,7 +351,7 @@ __global__ void __launch_bounds__(256) k_single(const ExecDesc* __restrict__ des
             const int s = tid + q * nth;
             if (s >= nel) break;
             cx<double> xa, xb;
-            untangle_at<T>([&](int64_t i) { return buf[lds_pad((int)i)]; }, L, s, tw[s], xa, xb);
+            untangle_at<T>([&](int i) { return buf[lds_pad(i)]; }, L, s, ldg(tw + s), xa, xb);
             acc[(2 * q) * nth + tid] += Target<K>::contrib(d, job, s, xa);
             if (2 * s != L) acc[(2 * q + 1) * nth + tid] += Target<K>::contrib(d, job, L - s, xb);
         }
@@ -347,19 +369,22 @@ __global__ void __launch_bounds__(256) k_single(const ExecDesc* __restrict__ des
 // ------------------------------------------------------------------ power of two, two passes
 
 // Column pass, item (desc, job, column tile): writes tmp[job][k1 L2 + n2].
+// Items come tile-major (all jobs of a tile together, terms m outer) and are
+// spread over the XCDs in contiguous ranges, so the jobs of one tile read the
+// shared inputs (g, c_n, the diagonals of a term) from the same L2.
 template <typename T, Src S>
 __global__ void __launch_bounds__(128) k_pass1(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-    const Item it = items[blockIdx.x];
+    const Item it = items[xcd_item(blockIdx.x, gridDim.x)];
     const ExecDesc& d = descs[it.desc];
     const FftGeom& g = geom_of<T>(d);
     const int job = it.a;
     cx<T>* out = reinterpret_cast<cx<T>*>(d.tmp) + (int64_t)job * g.L;
     col_pass<T>(
         lds, g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw), it.b,
-        [&](int64_t t) { return to_t<T>(Source<S>::load(d, job, t)); }, [&](int64_t i, cx<T> v) { out[i] = v; });
+        [&](int t) { return to_t<T>(Source<S>::load(d, job, t)); }, [&](int i, cx<T> v) { stg(out + i, v); });
 }
 
 // Row pass, item (desc, unit tile): TU units per workgroup; unit u holds rows
@@ -377,7 +402,7 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
     const ExecDesc& d = descs[it.desc];
     const FftGeom& g = geom_of<T>(d);
     const int L1 = g.L1, L2 = g.L2;
-    const int64_t L = g.L;
+    const int L = (int)g.L;
     const int TU = L2 >= 1024 ? 1 : 1024 / L2;
     const int unit0 = it.b * TU;
     const int tid = threadIdx.x, nth = blockDim.x;
@@ -401,7 +426,7 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
         const cx<T>* in = reinterpret_cast<const cx<T>*>(d.tmp) + (int64_t)job * L + (int64_t)my_row * L2;
         cx<T> v[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = in[lt + r * tpr];
+        for (int r = 0; r < 16; ++r) v[r] = ldg(in + lt + r * tpr);
         cx<T>* slice = buf + rs * sst;
         fft_reg<T>(v, slice, g.logL2, lt, true, tw, 2 * L);
 #pragma unroll
@@ -414,11 +439,11 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
             const int unit = unit0 + lu;
             const int ra = 2 * lu, rb = 2 * lu + 1;
             cx<double> xa, xb;
-            int64_t s;
+            int s;
             if (unit == 0) {
                 if (k2 < L2 / 2) {
-                    s = L1 / 2 + (int64_t)L1 * k2;
-                    untangle<T>(buf[rb * sst + lds_pad(k2)], buf[rb * sst + lds_pad(L2 - 1 - k2)], tw[s], xa, xb);
+                    s = L1 / 2 + L1 * k2;
+                    untangle<T>(buf[rb * sst + lds_pad(k2)], buf[rb * sst + lds_pad(L2 - 1 - k2)], ldg(tw + s), xa, xb);
                 } else if (k2 == L2 / 2) {
                     s = 0;
                     cx<T> z = buf[ra * sst];
@@ -426,12 +451,12 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
                     xb = {(double)z.re - (double)z.im, 0.0};
                 } else {
                     const int kk = k2 - L2 / 2;
-                    s = (int64_t)L1 * kk;
-                    untangle<T>(buf[ra * sst + lds_pad(kk)], buf[ra * sst + lds_pad(L2 - kk)], tw[s], xa, xb);
+                    s = L1 * kk;
+                    untangle<T>(buf[ra * sst + lds_pad(kk)], buf[ra * sst + lds_pad(L2 - kk)], ldg(tw + s), xa, xb);
                 }
             } else {
-                s = unit + (int64_t)L1 * k2;
-                untangle<T>(buf[ra * sst + lds_pad(k2)], buf[rb * sst + lds_pad(L2 - 1 - k2)], tw[s], xa, xb);
+                s = unit + L1 * k2;
+                untangle<T>(buf[ra * sst + lds_pad(k2)], buf[rb * sst + lds_pad(L2 - 1 - k2)], ldg(tw + s), xa, xb);
             }
             acc[(2 * q) * nth + tid] += Target<K>::contrib(d, job, s, xa);
             acc[(2 * q + 1) * nth + tid] += Target<K>::contrib(d, job, L - s, xb);
@@ -447,13 +472,13 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
         const int eps = tid + q * nth;
         const int lu = eps % TU, k2 = eps / TU;
         const int unit = unit0 + lu;
-        int64_t s;
+        int s;
         if (unit == 0) {
-            if (k2 < L2 / 2) s = L1 / 2 + (int64_t)L1 * k2;
+            if (k2 < L2 / 2) s = L1 / 2 + L1 * k2;
             else if (k2 == L2 / 2) s = 0;
-            else s = (int64_t)L1 * (k2 - L2 / 2);
+            else s = L1 * (k2 - L2 / 2);
         } else {
-            s = unit + (int64_t)L1 * k2;
+            s = unit + L1 * k2;
         }
         Target<K>::finish(d, s, acc[(2 * q) * nth + tid]);
         Target<K>::finish(d, L - s, acc[(2 * q + 1) * nth + tid]);
@@ -484,19 +509,19 @@ template <typename T, Src S>
 __global__ void __launch_bounds__(128) k_bs_col1(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
 {
     extern __shared__ unsigned char smem_raw[];
-    const Item it = items[blockIdx.x];
+    const Item it = items[xcd_item(blockIdx.x, gridDim.x)];
     const ExecDesc& d = descs[it.desc];
     const FftGeom& g = geom_of<T>(d);
     const int job = it.a;
-    const int64_t L = g.L;
+    const int L = (int)g.L;
     const cx<T>* chirp = reinterpret_cast<const cx<T>*>(g.chirp);
     cx<T>* base = bs_job<T>(d, g, job);
     col_pass<T>(
         reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw), it.b,
-        [&](int64_t t) {
-            return t < L ? cmul(to_t<T>(Source<S>::load(d, job, t)), chirp[t]) : cx<T>{(T)0, (T)0};
+        [&](int t) {
+            return t < L ? cmul(to_t<T>(Source<S>::load(d, job, t)), ldg(chirp + t)) : cx<T>{(T)0, (T)0};
         },
-        [&](int64_t i, cx<T> v) { base[i] = v; });
+        [&](int i, cx<T> v) { stg(base + i, v); });
 }
 
 // first transform, row pass: A in natural order to [P, 2P)
@@ -508,10 +533,10 @@ __global__ void __launch_bounds__(256) k_bs_row1(const ExecDesc* __restrict__ de
     const ExecDesc& d = descs[it.desc];
     const FftGeom& g = geom_of<T>(d);
     cx<T>* base = bs_job<T>(d, g, it.a);
-    const int64_t P = g.P;
+    const int P = (int)g.P;
     row_pass<T>(
         reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw), it.b,
-        [&](int64_t i) { return base[i]; }, [&](int64_t i, cx<T> v) { base[P + i] = v; });
+        [&](int i) { return ldg(base + i); }, [&](int i, cx<T> v) { stg(base + P + i, v); });
 }
 
 // second transform, column pass: input conj(A_t F(b~)_t)
@@ -523,11 +548,11 @@ __global__ void __launch_bounds__(128) k_bs_col2(const ExecDesc* __restrict__ de
     const ExecDesc& d = descs[it.desc];
     const FftGeom& g = geom_of<T>(d);
     cx<T>* base = bs_job<T>(d, g, it.a);
-    const int64_t P = g.P;
+    const int P = (int)g.P;
     const cx<T>* bl = reinterpret_cast<const cx<T>*>(g.bl);
     col_pass<T>(
         reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw), it.b,
-        [&](int64_t t) { return conj(cmul(base[P + t], bl[t])); }, [&](int64_t i, cx<T> v) { base[i] = v; });
+        [&](int t) { return conj(cmul(ldg(base + P + t), ldg(bl + t))); }, [&](int i, cx<T> v) { stg(base + i, v); });
 }
 
 // second transform, row pass: Z_s = c_s conj(E_s) / P for s < L, to [P, P+L)
@@ -539,14 +564,14 @@ __global__ void __launch_bounds__(256) k_bs_row2(const ExecDesc* __restrict__ de
     const ExecDesc& d = descs[it.desc];
     const FftGeom& g = geom_of<T>(d);
     cx<T>* base = bs_job<T>(d, g, it.a);
-    const int64_t P = g.P, L = g.L;
+    const int P = (int)g.P, L = (int)g.L;
     const cx<T>* chirp = reinterpret_cast<const cx<T>*>(g.chirp);
     const T invP = (T)1 / (T)P;
     row_pass<T>(
         reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw), it.b,
-        [&](int64_t i) { return base[i]; },
-        [&](int64_t s, cx<T> v) {
-            if (s < L) base[P + s] = cmul(chirp[s], cscale(conj(v), invP));
+        [&](int i) { return ldg(base + i); },
+        [&](int s, cx<T> v) {
+            if (s < L) stg(base + P + s, cmul(ldg(chirp + s), cscale(conj(v), invP)));
         });
 }
 
@@ -559,8 +584,9 @@ __global__ void __launch_bounds__(256) k_bs_untangle(const ExecDesc* __restrict_
     const Item it = items[blockIdx.x];
     const ExecDesc& d = descs[it.desc];
     const FftGeom& g = geom_of<T>(d);
-    const int64_t L = g.L, P = g.P;
-    const int64_t s = (int64_t)it.b * blockDim.x + threadIdx.x;
+    const int L = (int)g.L;
+    const int64_t P = g.P;
+    const int s = it.b * blockDim.x + threadIdx.x;
     if (s > L / 2) return;
     const cx<T>* utw = reinterpret_cast<const cx<T>*>(g.utw);
     const int njobs = kMulti ? d.nblk * d.M : 1;
@@ -569,7 +595,7 @@ __global__ void __launch_bounds__(256) k_bs_untangle(const ExecDesc* __restrict_
         const int job = kMulti ? (iter % d.nblk) * d.M + iter / d.nblk : 0;
         const cx<T>* Z = reinterpret_cast<const cx<T>*>(d.tmp) + (int64_t)job * 2 * P + P;
         cx<double> xa, xb;
-        untangle_at<T>([&](int64_t i) { return Z[i]; }, L, s, utw[s], xa, xb);
+        untangle_at<T>([&](int i) { return ldg(Z + i); }, L, s, ldg(utw + s), xa, xb);
         a0 += Target<K>::contrib(d, job, s, xa);
         if (2 * s != L) a1 += Target<K>::contrib(d, job, L - s, xb);
     }
@@ -599,20 +625,20 @@ __global__ void __launch_bounds__(256) k_bs_single(const ExecDesc* __restrict__ 
     const int njobs = Source<S>::kMulti ? d.nblk * d.M : 1;
     for (int job = 0; job < njobs; ++job) {
         for (int t = tid; t < P; t += nth)
-            buf[lds_pad(t)] = t < L ? cmul(to_t<T>(Source<S>::load(d, job, t)), chirp[t]) : cx<T>{(T)0, (T)0};
+            buf[lds_pad(t)] = t < L ? cmul(to_t<T>(Source<S>::load(d, job, t)), ldg(chirp + t)) : cx<T>{(T)0, (T)0};
         __syncthreads();
         lds_fft<T>(buf, g.logP, 1, tw, 2 * g.P);
-        for (int t = tid; t < P; t += nth) buf[lds_pad(t)] = conj(cmul(buf[lds_pad(t)], bl[t]));
+        for (int t = tid; t < P; t += nth) buf[lds_pad(t)] = conj(cmul(buf[lds_pad(t)], ldg(bl + t)));
         __syncthreads();
         lds_fft<T>(buf, g.logP, 1, tw, 2 * g.P);
-        for (int t = tid; t < L; t += nth) buf[lds_pad(t)] = cmul(chirp[t], cscale(conj(buf[lds_pad(t)]), invP));
+        for (int t = tid; t < L; t += nth) buf[lds_pad(t)] = cmul(ldg(chirp + t), cscale(conj(buf[lds_pad(t)]), invP));
         __syncthreads();
 #pragma unroll 2
         for (int q = 0; q < kSlots / 2; ++q) {
             const int sx = tid + q * nth;
             if (sx >= nel) break;
             cx<double> xa, xb;
-            untangle_at<T>([&](int64_t i) { return buf[lds_pad((int)i)]; }, L, sx, utw[sx], xa, xb);
+            untangle_at<T>([&](int i) { return buf[lds_pad(i)]; }, L, sx, ldg(utw + sx), xa, xb);
             acc[(2 * q) * nth + tid] += Target<K>::contrib(d, job, sx, xa);
             if (2 * sx != L) acc[(2 * q + 1) * nth + tid] += Target<K>::contrib(d, job, L - sx, xb);
         }
@@ -625,6 +651,97 @@ __global__ void __launch_bounds__(256) k_bs_single(const ExecDesc* __restrict__ 
         Target<K>::finish(d, sx, acc[(2 * q) * nth + tid]);
         if (2 * sx != L) Target<K>::finish(d, L - sx, acc[(2 * q + 1) * nth + tid]);
     }
+}
+
+// ------------------------------------------------------------------ job-parallel single workgroup
+//
+// For calls with few instances the single-workgroup kinds run one workgroup
+// per (instance, job): the transform of that job, its untangling and its sink
+// contributions, written to part[job][s] (doubles, s = 0..L); a second kernel
+// adds the jobs in a fixed order and stores the result.
+
+template <typename T>
+__device__ __forceinline__ double* job_part(const ExecDesc& d, int job)
+{
+    return reinterpret_cast<double*>(d.tmp) + (int64_t)job * (d.geo.L + 1);
+}
+
+template <typename T, Src S, Sink K>
+__global__ void __launch_bounds__(256) k_single_job(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const Item it = items[blockIdx.x];
+    const ExecDesc& d = descs[it.desc];
+    const FftGeom& g = geom_of<T>(d);
+    const int job = it.a;
+    const int L = (int)g.L;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
+    for (int t = tid; t < L; t += nth) buf[lds_pad(t)] = to_t<T>(Source<S>::load(d, job, t));
+    __syncthreads();
+    lds_fft<T>(buf, g.logL, 1, tw, 2 * g.L);
+    double* part = job_part<T>(d, job);
+    for (int s = tid; s <= L / 2; s += nth) {
+        cx<double> xa, xb;
+        untangle_at<T>([&](int i) { return buf[lds_pad(i)]; }, L, s, ldg(tw + s), xa, xb);
+        stg(part + s, Target<K>::contrib(d, job, s, xa));
+        if (2 * s != L) stg(part + L - s, Target<K>::contrib(d, job, L - s, xb));
+    }
+}
+
+template <typename T, Src S, Sink K>
+__global__ void __launch_bounds__(256) k_bs_single_job(const ExecDesc* __restrict__ descs,
+                                                       const Item* __restrict__ items)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const Item it = items[blockIdx.x];
+    const ExecDesc& d = descs[it.desc];
+    const FftGeom& g = geom_of<T>(d);
+    const int job = it.a;
+    const int L = (int)g.L, P = (int)g.P;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
+    const cx<T>* chirp = reinterpret_cast<const cx<T>*>(g.chirp);
+    const cx<T>* bl = reinterpret_cast<const cx<T>*>(g.bl);
+    const cx<T>* utw = reinterpret_cast<const cx<T>*>(g.utw);
+    const T invP = (T)1 / (T)P;
+    for (int t = tid; t < P; t += nth)
+        buf[lds_pad(t)] = t < L ? cmul(to_t<T>(Source<S>::load(d, job, t)), ldg(chirp + t)) : cx<T>{(T)0, (T)0};
+    __syncthreads();
+    lds_fft<T>(buf, g.logP, 1, tw, 2 * g.P);
+    for (int t = tid; t < P; t += nth) buf[lds_pad(t)] = conj(cmul(buf[lds_pad(t)], ldg(bl + t)));
+    __syncthreads();
+    lds_fft<T>(buf, g.logP, 1, tw, 2 * g.P);
+    for (int t = tid; t < L; t += nth) buf[lds_pad(t)] = cmul(ldg(chirp + t), cscale(conj(buf[lds_pad(t)]), invP));
+    __syncthreads();
+    double* part = job_part<T>(d, job);
+    for (int s = tid; s <= L / 2; s += nth) {
+        cx<double> xa, xb;
+        untangle_at<T>([&](int i) { return buf[lds_pad(i)]; }, L, s, ldg(utw + s), xa, xb);
+        stg(part + s, Target<K>::contrib(d, job, s, xa));
+        if (2 * s != L) stg(part + L - s, Target<K>::contrib(d, job, L - s, xb));
+    }
+}
+
+// item (desc, tile of 256 outputs): sum over jobs, terms m outer and blocks k inner
+template <Sink K>
+__global__ void __launch_bounds__(256) k_job_reduce(const ExecDesc* __restrict__ descs,
+                                                    const Item* __restrict__ items)
+{
+    const Item it = items[blockIdx.x];
+    const ExecDesc& d = descs[it.desc];
+    const int L = (int)d.geo.L;
+    const int s = it.b * blockDim.x + threadIdx.x;
+    if (s > L) return;
+    const int njobs = d.nblk * d.M;
+    double acc = 0.0;
+    for (int iter = 0; iter < njobs; ++iter) {
+        const int job = (iter % d.nblk) * d.M + iter / d.nblk;
+        acc += ldg(reinterpret_cast<const double*>(d.tmp) + (int64_t)job * (L + 1) + s);
+    }
+    Target<K>::finish(d, s, acc);
 }
 
 // ------------------------------------------------------------------ host side
@@ -655,6 +772,15 @@ cjt_status allow_lds(K kernel, size_t bytes)
     return CJT_OK;
 }
 
+// Timing labels live as long as the library (a handful of distinct strings).
+const char* intern(const std::string& x)
+{
+    static std::mutex mu;
+    static std::set<std::string> names;
+    std::lock_guard<std::mutex> lk(mu);
+    return names.insert(x).first->c_str();
+}
+
 template <typename K, typename... Args>
 cjt_status go(K kernel, const Launch& L, hipStream_t s, Args... args)
 {
@@ -683,6 +809,9 @@ cjt_status run(const Launch& L, const ExecDesc* dd, const Item* it, hipStream_t 
     case Kind::BsCol2: return go(k_bs_col2<T>, L, s, dd, it);
     case Kind::BsRow2: return go(k_bs_row2<T>, L, s, dd, it);
     case Kind::BsUntangle: return go(k_bs_untangle<T, K, kMulti>, L, s, dd, it);
+    case Kind::FftJobs: return go(k_single_job<T, S, K>, L, s, dd, it);
+    case Kind::BsJobs: return go(k_bs_single_job<T, S, K>, L, s, dd, it);
+    case Kind::JobReduce: return go(k_job_reduce<K>, L, s, dd, it);
     default: return fail(CJT_EINVAL, "not an FFT launch");
     }
 }
@@ -703,11 +832,24 @@ cjt_status launch_fft(const Launch& L, const ExecDesc* dd, const Item* it, hipSt
     return fail(CJT_EINVAL, "unknown transform pairing");
 }
 
+// The job-parallel mode applies to single-workgroup lengths with more than
+// one job; add_fft and fft_tmp_bytes decide it with this one predicate.
+static bool job_mode(const FftGeom& g, int64_t jobs, bool job_parallel)
+{
+    return job_parallel && jobs > 1 && g.single;
+}
+
+// Job of iteration `it` in the order terms m outer, blocks k inner.
+static int job_at(const ExecDesc& d, int it, bool multi)
+{
+    return multi ? (it % d.nblk) * d.M + it / d.nblk : 0;
+}
+
 // Launch classes of one engine pass: instances are bucketed by kernel and
 // workgroup size; each bucket is one launch over its items.
 cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sink, bool fp32, int stream,
                    const char* name_cols, const char* name_rows, const std::vector<double>& flops,
-                   const std::vector<double>& bytes)
+                   const std::vector<double>& bytes, bool job_parallel)
 {
     const bool multi = (src == Src::FwdAsy || src == Src::InvAsy);
     const bool f32 = fp32 && multi;
@@ -733,7 +875,18 @@ cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sin
         const int jobs = multi ? d.nblk * d.M : 1;
         if (jobs <= 0) continue;
         const double fl = flops[i], by = bytes[i];
-        if (!g.bluestein && g.single) {
+        if (multi && job_mode(g, jobs, job_parallel)) {
+            const int64_t F = g.bluestein ? g.P : g.L;
+            Bucket& b = bucket(g.bluestein ? Kind::BsJobs : Kind::FftJobs, clamp_nth(F), name_cols);
+            for (int j = 0; j < jobs; ++j) b.items.push_back(Item{i, j, 0, 0});
+            b.lds = std::max(b.lds, lds_bytes(F, esz));
+            b.flops += 0.5 * fl;
+            b.bytes += 0.5 * by;
+            Bucket& br = bucket(Kind::JobReduce, 256, name_rows);
+            for (int64_t t = 0; t < (g.L + 1 + 255) / 256; ++t) br.items.push_back(Item{i, 0, (int32_t)t, 0});
+            br.flops += 0.5 * fl;
+            br.bytes += 0.5 * by;
+        } else if (!g.bluestein && g.single) {
             const int nth = clamp_nth(g.L);
             if ((g.L / 2 + 1 + nth - 1) / nth > kSlots / 2) return fail(CJT_EUNSUPPORTED, "single-pass length");
             Bucket& b = bucket(Kind::FftSingle, nth, name_cols);
@@ -747,8 +900,8 @@ cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sin
             const int TU = g.L2 >= 1024 ? 1 : 1024 / g.L2;
             const int nth2 = 2 * TU * (g.L2 / 16);
             Bucket& b1 = bucket(Kind::FftPass1, 128, name_cols);
-            for (int j = 0; j < jobs; ++j)
-                for (int t = 0; t < g.L2 / TC; ++t) b1.items.push_back(Item{i, j, t, 0});
+            for (int t = 0; t < g.L2 / TC; ++t)
+                for (int it = 0; it < jobs; ++it) b1.items.push_back(Item{i, job_at(d, it, multi), t, 0});
             b1.lds = std::max(b1.lds, (size_t)TC * slice_stride(g.L1) * esz);
             b1.flops += 0.5 * fl;
             b1.bytes += 0.5 * by;
@@ -775,8 +928,13 @@ cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sin
                 const bool col = (q % 2) == 0;
                 Bucket& b = bucket(ks[q], col ? 128 : nthr, name_cols);
                 const int tiles = col ? g.L2 / TC : g.L1 / TR;
-                for (int j = 0; j < jobs; ++j)
-                    for (int t = 0; t < tiles; ++t) b.items.push_back(Item{i, j, t, 0});
+                if (q == 0) {  // tile-major, as the power-of-two column pass
+                    for (int t = 0; t < tiles; ++t)
+                        for (int it = 0; it < jobs; ++it) b.items.push_back(Item{i, job_at(d, it, multi), t, 0});
+                } else {
+                    for (int j = 0; j < jobs; ++j)
+                        for (int t = 0; t < tiles; ++t) b.items.push_back(Item{i, j, t, 0});
+                }
                 b.lds = std::max(b.lds, col ? (size_t)TC * slice_stride(g.L1) * esz : (size_t)TR * slice_stride(g.L2) * esz);
                 b.flops += 0.125 * fl;
                 b.bytes += 0.125 * by;
@@ -787,9 +945,30 @@ cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sin
             bu.bytes += 0.5 * by;
         }
     }
+    // timing labels: the caller's column / row names, with the chirp-z and
+    // single-workgroup kinds told apart
+    auto label = [&](Kind k, const char* nm) -> const char* {
+        if (!nm) return nullptr;
+        const char* sfx = "";
+        switch (k) {
+        case Kind::FftSingle: sfx = "_single"; break;
+        case Kind::BsSingle: sfx = "_bs_single"; break;
+        case Kind::BsCol1:
+        case Kind::BsCol2: sfx = "_bs_cols"; break;
+        case Kind::BsRow1:
+        case Kind::BsRow2: sfx = "_bs_rows"; break;
+        case Kind::BsUntangle: sfx = "_bs_untangle"; break;
+        case Kind::FftJobs: sfx = "_jobs"; break;
+        case Kind::BsJobs: sfx = "_bs_jobs"; break;
+        case Kind::JobReduce: sfx = "_job_reduce"; break;
+        default: break;
+        }
+        return intern(std::string(nm) + sfx);
+    };
     // launch order: single-workgroup kinds, then the two-pass chains in dependency order
-    const Kind order[] = {Kind::FftSingle, Kind::BsSingle, Kind::FftPass1, Kind::FftPass2, Kind::BsCol1,
-                          Kind::BsRow1,    Kind::BsCol2,   Kind::BsRow2,   Kind::BsUntangle};
+    const Kind order[] = {Kind::FftSingle, Kind::BsSingle, Kind::FftJobs, Kind::BsJobs,     Kind::JobReduce,
+                          Kind::FftPass1,  Kind::FftPass2, Kind::BsCol1,  Kind::BsRow1,     Kind::BsCol2,
+                          Kind::BsRow2,    Kind::BsUntangle};
     for (Kind k : order) {
         for (auto& b : bk) {
             if (b.kind != k || b.items.empty()) continue;
@@ -811,7 +990,7 @@ cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sin
             } else {
                 L.lds = b.lds;
             }
-            L.name = b.name;
+            L.name = label(k, b.name);
             L.flops = b.flops;
             L.bytes = b.bytes;
             pr.items.insert(pr.items.end(), b.items.begin(), b.items.end());
@@ -979,6 +1158,13 @@ cjt_status make_chirp_tables(FftGeom* g, bool fp32, hipStream_t st)
     }
     CJT_HIP_TRY(hipStreamSynchronize(st));
     return CJT_OK;
+}
+
+size_t fft_tmp_bytes(const FftGeom& g, int64_t jobs, bool fp32, bool job_parallel)
+{
+    if (jobs <= 0) return 0;
+    if (job_mode(g, jobs, job_parallel)) return sizeof(double) * (size_t)jobs * (size_t)(g.L + 1);
+    return (size_t)jobs * fft_job_bytes(g.L, fp32);
 }
 
 size_t fft_job_bytes(int64_t L, bool fp32)

@@ -172,8 +172,8 @@ __device__ __forceinline__ void stage_load(StageRegs& r, const d4* __restrict__ 
     for (int h = 0; h < 2; ++h) {
         const int n = n0 + lane + 64 * h;
         if (n >= lo && n < hi) {
-            r.co[h] = co[n];
-            r.c[h] = c ? c[n] : 0.0;
+            r.co[h] = ldg(co + n);
+            r.c[h] = c ? ldg(c + n) : 0.0;
         } else {
             r.co[h] = d4{0.0, 0.0, 0.0, 0.0};
             r.c[h] = 0.0;
@@ -212,7 +212,7 @@ template <bool kSplit>
 __global__ void __launch_bounds__(64) k_rec_fwd(const ExecDesc* __restrict__ descs, const Item* __restrict__ items,
                                                 int S)
 {
-    __shared__ Stage stg[2];
+    __shared__ Stage sbuf[2];
     const Item it = items[blockIdx.x];
     const ExecDesc& d = descs[it.desc];
     const TaskView tk = task_of(d, it.a);
@@ -244,13 +244,13 @@ __global__ void __launch_bounds__(64) k_rec_fwd(const ExecDesc* __restrict__ des
     int buf = 0;
     if (nb > 0) {
         stage_load(rg, co, d.in, lo + (nb - 1) * kBlk, lo, hi, lane);
-        stage_store(stg[0], rg, lane);
+        stage_store(sbuf[0], rg, lane);
     }
     __syncthreads();
     for (int b = nb - 1; b >= 0; --b) {
         const int b0 = lo + b * kBlk;
         if (b > 0) stage_load(rg, co, d.in, b0 - kBlk, lo, hi, lane);
-        const Stage& St = stg[buf];
+        const Stage& St = sbuf[buf];
         const int top = min(kBlk, hi - b0) - 1;
         if (mode == 0) {
 #pragma unroll 4
@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(64) k_rec_fwd(const ExecDesc* __restrict__ des
                     }
             }
         }
-        if (b > 0) stage_store(stg[buf ^ 1], rg, lane);
+        if (b > 0) stage_store(sbuf[buf ^ 1], rg, lane);
         __syncthreads();
         buf ^= 1;
     }
@@ -292,7 +292,7 @@ __global__ void __launch_bounds__(64) k_rec_fwd(const ExecDesc* __restrict__ des
 #pragma unroll
         for (int q = 0; q < kPPT; ++q) {
             const int idx = lane + 64 * q;
-            if (idx < tk.np) d.p[tk.p0 + idx] = mode == 0 ? s1[0][q] : s2[0][q];
+            if (idx < tk.np) stg(d.p + tk.p0 + idx, mode == 0 ? s1[0][q] : s2[0][q]);
         }
     } else {
         double* rec = d.seg + (int64_t)it.c * kRec;
@@ -301,8 +301,8 @@ __global__ void __launch_bounds__(64) k_rec_fwd(const ExecDesc* __restrict__ des
             const int idx = lane + 64 * q;
 #pragma unroll
             for (int ch = 0; ch < NC; ++ch) {
-                rec[(2 * ch) * 64 * kPPT + idx] = s1[ch][q];
-                rec[(2 * ch + 1) * 64 * kPPT + idx] = s2[ch][q];
+                stg(rec + (2 * ch) * 64 * kPPT + idx, s1[ch][q]);
+                stg(rec + (2 * ch + 1) * 64 * kPPT + idx, s2[ch][q]);
             }
         }
     }
@@ -326,12 +326,12 @@ __global__ void __launch_bounds__(64) k_rec_fwd_combine(const ExecDesc* __restri
 #pragma unroll 4
         for (int s = nseg - 1; s >= 0; --s) {
             const double* rec = d.seg + (int64_t)(it.c + s) * kRec + idx;
-            const double nx = rec[0] + fma(rec[2 * R], x, rec[4 * R] * y);
-            const double ny = rec[R] + fma(rec[3 * R], x, rec[5 * R] * y);
+            const double nx = ldg(rec) + fma(ldg(rec + 2 * R), x, ldg(rec + 4 * R) * y);
+            const double ny = ldg(rec + R) + fma(ldg(rec + 3 * R), x, ldg(rec + 5 * R) * y);
             x = nx;
             y = ny;
         }
-        if (idx < tk.np) d.p[tk.p0 + idx] = tk.mode == 0 ? x : y;
+        if (idx < tk.np) stg(d.p + tk.p0 + idx, tk.mode == 0 ? x : y);
     }
 }
 
@@ -347,7 +347,7 @@ __global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ des
                                                 int S)
 {
     __shared__ double red[kChunk][64 + 1];
-    __shared__ Stage stg[2];
+    __shared__ Stage sbuf[2];
     const Item it = items[blockIdx.x];
     const ExecDesc& d = descs[it.desc];
     const TaskView tk = task_of(d, it.a);
@@ -377,10 +377,10 @@ __global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ des
             pv[NC - 1][q] = 0.0;
             ev[NC - 1][q] = 1.0;
         } else if (split) {
-            pv[0][q] = rec[4 * R + idx];
-            ev[0][q] = rec[5 * R + idx];
+            pv[0][q] = ldg(rec + 4 * R + idx);
+            ev[0][q] = ldg(rec + 5 * R + idx);
         } else {
-            pv[0][q] = act ? d.p[j] : 0.0;  // pi_0 = g_j (scaled recurrence)
+            pv[0][q] = act ? ldg(d.p + j) : 0.0;  // pi_0 = g_j (scaled recurrence)
             ev[0][q] = 0.0;                 // e_0 = 0 (modified) / P_{-1} = 0 (three-term)
         }
         grid_point(j, G, mode, xh[q], xl[q]);
@@ -393,13 +393,13 @@ __global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ des
     int buf = 0;
     if (nb > 0) {
         stage_load(rg, co, nullptr, lo, lo, hi, lane);
-        stage_store(stg[0], rg, lane);
+        stage_store(sbuf[0], rg, lane);
     }
     __syncthreads();
     for (int b = 0; b < nb; ++b) {
         const int b0 = lo + b * kBlk;
         if (b + 1 < nb) stage_load(rg, co, nullptr, b0 + kBlk, lo, hi, lane);
-        const Stage& St = stg[buf];
+        const Stage& St = sbuf[buf];
         const int bend = min(kBlk, hi - b0);
         for (int c0 = 0; c0 < bend; c0 += kChunk) {
             const int nend = min(kChunk, bend - c0);
@@ -442,12 +442,12 @@ __global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ des
                     for (int l = 0; l < 16; ++l) sum += red[dd][qq * 16 + l];
                     sum += __shfl_xor(sum, 1);
                     sum += __shfl_xor(sum, 2);
-                    if (qq == 0) part[b0 + c0 + dd] = sum;
+                    if (qq == 0) stg(part + b0 + c0 + dd, sum);
                 }
                 __syncthreads();
             }
         }
-        if (b + 1 < nb) stage_store(stg[buf ^ 1], rg, lane);
+        if (b + 1 < nb) stage_store(sbuf[buf ^ 1], rg, lane);
         __syncthreads();
         buf ^= 1;
     }
@@ -457,8 +457,8 @@ __global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ des
             const int idx = lane + 64 * q;
 #pragma unroll
             for (int ch = 0; ch < NC; ++ch) {
-                rec[(2 * ch) * R + idx] = pv[ch][q];
-                rec[(2 * ch + 1) * R + idx] = ev[ch][q];
+                stg(rec + (2 * ch) * R + idx, pv[ch][q]);
+                stg(rec + (2 * ch + 1) * R + idx, ev[ch][q]);
             }
         }
     }
@@ -476,14 +476,14 @@ __global__ void __launch_bounds__(64) k_rec_inv_init(const ExecDesc* __restrict_
     constexpr int R = 64 * kPPT;
     for (int q = 0; q < kPPT; ++q) {
         const int idx = threadIdx.x + 64 * q;
-        double x = idx < tk.np ? d.p[tk.p0 + idx] : 0.0, y = 0.0;
+        double x = idx < tk.np ? ldg(d.p + tk.p0 + idx) : 0.0, y = 0.0;
         for (int s = 0; s < nseg; ++s) {
             double* rec = d.seg + (int64_t)(it.c + s) * kRec + idx;
-            rec[4 * R] = x;
-            rec[5 * R] = y;
+            stg(rec + 4 * R, x);
+            stg(rec + 5 * R, y);
             if (s + 1 < nseg) {
-                const double nx = fma(rec[0], x, rec[2 * R] * y);
-                const double ny = fma(rec[R], x, rec[3 * R] * y);
+                const double nx = fma(ldg(rec), x, ldg(rec + 2 * R) * y);
+                const double ny = fma(ldg(rec + R), x, ldg(rec + 3 * R) * y);
                 x = nx;
                 y = ny;
             }
@@ -492,35 +492,38 @@ __global__ void __launch_bounds__(64) k_rec_inv_init(const ExecDesc* __restrict_
 }
 
 // out[n] = s_n (Hahn part + sum over tasks t with cut_t > n of part_t[n]).
-// Item (desc, tile of 32 degrees); 8 groups of 32 lanes split the tasks
-// (t = group mod 8) and are added in a fixed order.  Tasks are sorted by
-// decreasing cut, so the contributing ones form a prefix.
+// Item (desc, tile of 256/GR degrees); GR groups of lanes split the tasks
+// (t = group mod GR) and are added in a fixed order (GR = 8 for instances
+// with many tasks, 1 otherwise).  Tasks are sorted by decreasing cut, so the
+// contributing ones form a prefix.
+template <int GR>
 __global__ void __launch_bounds__(256) k_rec_inv_reduce(const ExecDesc* __restrict__ descs,
                                                         const Item* __restrict__ items)
 {
-    __shared__ double red[8][33];
+    constexpr int DN = 256 / GR;  // degrees per workgroup
+    __shared__ double red[GR][DN + 1];
     const Item it = items[blockIdx.x];
     const ExecDesc& d = descs[it.desc];
-    const int dn = threadIdx.x & 31, grp = threadIdx.x >> 5;
-    const int64_t n = (int64_t)it.b * 32 + dn;
+    const int dn = threadIdx.x % DN, grp = threadIdx.x / DN;
+    const int64_t n = (int64_t)it.b * DN + dn;
     int lo = 0, hi = d.ntasks;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (d.tasks[mid].cut > n) lo = mid + 1;
+        if (ldg(&d.tasks[mid].cut) > n) lo = mid + 1;
         else hi = mid;
     }
     const int T = lo;
     double acc = 0.0;
 #pragma unroll 4
-    for (int t = grp; t < T; t += 8) acc += d.part[d.tasks[t].off + n];
+    for (int t = grp; t < T; t += GR) acc += ldg(d.part + ldg(&d.tasks[t].off) + n);
     red[grp][dn] = acc;
     __syncthreads();
     if (grp == 0 && n <= d.N) {
         double tot = 0.0;
 #pragma unroll
-        for (int g = 0; g < 8; ++g) tot += red[g][dn];
-        const double base = d.nblk > 0 ? d.out[n] : 0.0;
-        d.out[n] = d.s[n] * (base + tot);
+        for (int g = 0; g < GR; ++g) tot += red[g][dn];
+        const double base = d.nblk > 0 ? ldg(d.out + n) : 0.0;
+        stg(d.out + n, ldg(d.s + n) * (base + tot));
     }
 }
 
@@ -532,12 +535,15 @@ int32_t rec_segment_length(const Program& pr, const std::vector<const RecTask*>&
         const int v = atoi(e);
         if (v > 0) return std::max(kBlk, (v + kBlk - 1) / kBlk * kBlk);
     }
-    // total chain steps; no chain should be much longer than an even share
-    // of them over ~1024 concurrent waves
+    // total chain steps W: with one wave per SIMD busy on FP64 issue, the
+    // recurrence phase takes about W / 1024 steps of time; a chain longer than
+    // that would be the critical path, so chains are cut to that share, but
+    // never below 256 steps (there the extra chains and launches cost more
+    // than the chain itself)
     double W = 0.0;
     for (size_t i = 0; i < pr.descs.size(); ++i)
         for (int t = 0; t < pr.descs[i].ntasks; ++t) W += (double)tasks[i][t].cut;
-    const double S = std::max(1024.0, std::ceil(W / 1024.0));
+    const double S = std::max(256.0, std::ceil(W / 1024.0));
     const int Si = (int)std::min(S, 1.0e9);
     return (Si + kBlk - 1) / kBlk * kBlk;
 }
@@ -565,6 +571,18 @@ Launch rec_launch(Kind k, int stream, int nth, int32_t S, const char* name, doub
     L.flops = flops;
     L.bytes = bytes;
     return L;
+}
+
+// Longest chains first over the whole call, so that no long chain of a late
+// instance starts after the short ones have drained (ties keep their order).
+void by_length(std::vector<Item>& items, const Program& pr, const std::vector<const RecTask*>& tasks, int32_t S)
+{
+    auto len = [&](const Item& it) {
+        const int cut = tasks[it.desc][it.a].cut;
+        const int ns = seg_count(cut, S);
+        return ns == 1 ? cut : seg_len(cut, ns);
+    };
+    std::stable_sort(items.begin(), items.end(), [&](const Item& x, const Item& y) { return len(x) > len(y); });
 }
 
 void push(Program& pr, Launch L, const std::vector<Item>& items)
@@ -596,6 +614,8 @@ void add_rec_fwd(Program& pr, const std::vector<const RecTask*>& tasks, int32_t 
             }
         }
     }
+    by_length(segs, pr, tasks, S);
+    by_length(whole, pr, tasks, S);
     push(pr, rec_launch(Kind::RecFwdSeg, stream, 64, S, "rec_forward", flops * 0.5, bytes * 0.5), segs);
     push(pr, rec_launch(Kind::RecFwd, stream, 64, S, "rec_forward", segs.empty() ? flops : flops * 0.5,
                         segs.empty() ? bytes : bytes * 0.5),
@@ -624,6 +644,8 @@ void add_rec_inv(Program& pr, const std::vector<const RecTask*>& tasks, int32_t 
             }
         }
     }
+    by_length(maps, pr, tasks, S);
+    by_length(all, pr, tasks, S);
     push(pr, rec_launch(Kind::RecInvMaps, stream, 64, S, "rec_inverse_maps", 0.0, 0.0), maps);
     push(pr, rec_launch(Kind::RecInvInit, stream, 64, S, "rec_inverse_init", 0.0, 0.0), init);
     push(pr, rec_launch(Kind::RecInv, stream, 64, S, "rec_inverse", flops, bytes), all);
@@ -631,10 +653,22 @@ void add_rec_inv(Program& pr, const std::vector<const RecTask*>& tasks, int32_t 
 
 void add_rec_inv_reduce(Program& pr, int stream, double bytes)
 {
-    std::vector<Item> items;
-    for (size_t i = 0; i < pr.descs.size(); ++i)
-        for (int64_t t = 0; t < (pr.descs[i].N + 1 + 31) / 32; ++t) items.push_back(Item{(int32_t)i, 0, (int32_t)t, 0});
-    push(pr, rec_launch(Kind::RecInvReduce, stream, 256, 0, "rec_inverse_reduce", 0.0, bytes), items);
+    // many tasks per degree (large N): eight groups share them; otherwise one
+    std::vector<Item> wide, narrow;
+    for (size_t i = 0; i < pr.descs.size(); ++i) {
+        const bool many = pr.descs[i].ntasks >= 1024;
+        const int dn = many ? 32 : 256;
+        for (int64_t t = 0; t < (pr.descs[i].N + 1 + dn - 1) / dn; ++t)
+            (many ? wide : narrow).push_back(Item{(int32_t)i, 0, (int32_t)t, 0});
+    }
+    const double tot = (double)(wide.size() * 32 + narrow.size() * 256);
+    Launch L = rec_launch(Kind::RecInvReduce, stream, 256, 0, "rec_inverse_reduce", 0.0, 0.0);
+    L.acc_off = 8;  // groups
+    L.bytes = tot > 0 ? bytes * (double)(wide.size() * 32) / tot : 0.0;
+    push(pr, L, wide);
+    L.acc_off = 1;
+    L.bytes = tot > 0 ? bytes * (double)(narrow.size() * 256) / tot : 0.0;
+    push(pr, L, narrow);
 }
 
 cjt_status launch_rec(const Launch& L, const ExecDesc* dd, const Item* it, hipStream_t s)
@@ -649,7 +683,10 @@ cjt_status launch_rec(const Launch& L, const ExecDesc* dd, const Item* it, hipSt
     case Kind::RecInvMaps: hipLaunchKernelGGL(k_rec_inv<true>, grid, block, 0, s, dd, it, L.seg); break;
     case Kind::RecInvInit: hipLaunchKernelGGL(k_rec_inv_init, grid, block, 0, s, dd, it); break;
     case Kind::RecInv: hipLaunchKernelGGL(k_rec_inv<false>, grid, block, 0, s, dd, it, L.seg); break;
-    case Kind::RecInvReduce: hipLaunchKernelGGL(k_rec_inv_reduce, grid, block, 0, s, dd, it); break;
+    case Kind::RecInvReduce:
+        if (L.acc_off == 8) hipLaunchKernelGGL(k_rec_inv_reduce<8>, grid, block, 0, s, dd, it);
+        else hipLaunchKernelGGL(k_rec_inv_reduce<1>, grid, block, 0, s, dd, it);
+        break;
     default: return fail(CJT_EINVAL, "not a recurrence launch");
     }
     CJT_HIP_TRY(hipGetLastError());
