@@ -48,6 +48,8 @@ struct FftGeom {
     int32_t L1, L2;   // two-pass split of the power-of-two length (L, or P for chirp-z)
     int32_t logL1, logL2;
     const void* tw;   // [2L'] e^{i pi q / L'}, L' = L (power of two) or P (chirp-z)
+    const void* tw1;  // [2 L1] e^{i pi q / L1}: stages of the column FFTs (two passes only)
+    const void* tw2;  // [2 L2] e^{i pi q / L2}: stages of the row FFTs
     // chirp-z only
     int32_t bluestein;
     int32_t logP;
@@ -217,6 +219,7 @@ enum class Kind : int32_t {
     Patch,           // in/out pointers of every descriptor from the call's base pointers
     FftSingle,       // whole power-of-two transform in one workgroup, all jobs of an instance
     FftPass1,        // column pass of a two-pass transform, one (job, column tile)
+    FftPass1Inv,     // inverse Hahn blocks: column pass of every block of one (term, column tile)
     FftPass2,        // row pass + untangling + sink, all jobs of an instance, one row tile
     BsSingle,        // chirp-z transform in one workgroup
     BsCol1, BsRow1,  // chirp-z, first transform (two passes)

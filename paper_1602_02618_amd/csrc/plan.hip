@@ -551,6 +551,10 @@ cjt_status fft_geometry(int64_t L, bool fp32, hipStream_t st, FftGeom* g)
         cjt_status s = fft_twiddles_cached(L, fp32, st, &x.tw);
         if (s != CJT_OK) return s;
         split(&x, x.logL, L);
+        if (!x.single) {
+            if ((s = fft_twiddles_cached(x.L1, fp32, st, &x.tw1)) != CJT_OK) return s;
+            if ((s = fft_twiddles_cached(x.L2, fp32, st, &x.tw2)) != CJT_OK) return s;
+        }
     } else {
         x.bluestein = 1;
         x.logP = ilog2_ceil(2 * L - 1);
@@ -558,6 +562,10 @@ cjt_status fft_geometry(int64_t L, bool fp32, hipStream_t st, FftGeom* g)
         cjt_status s = fft_twiddles_cached(x.P, fp32, st, &x.tw);
         if (s != CJT_OK) return s;
         split(&x, x.logP, x.P);
+        if (!x.single) {
+            if ((s = fft_twiddles_cached(x.L1, fp32, st, &x.tw1)) != CJT_OK) return s;
+            if ((s = fft_twiddles_cached(x.L2, fp32, st, &x.tw2)) != CJT_OK) return s;
+        }
         s = make_chirp_tables(&x, fp32, st);
         if (s != CJT_OK) return s;
     }

@@ -82,11 +82,16 @@ struct Source<Src::InvAsy> {
         if (j == 0 || j == G) return uv.re * g;
         return 0.5 * g * (mirror ? uv.re - uv.im : uv.re + uv.im);
     }
-    // (r_q, r_{q+1}) for even q.  q <= G - 1 reads points q, q+1; q >= G + 1
-    // reads 2G - q - 1, 2G - q (the mirror); q = G straddles the two halves.
     __device__ static cx<double> load(const ExecDesc& d, int job, int t)
     {
-        const int k = job / d.M, m = job - k * d.M;
+        const int k = job / d.M;
+        return pair(d, k, job - k * d.M, t);
+    }
+    // (r_q, r_{q+1}) of term m on block k's window for q = 2t.  q <= G - 1
+    // reads points q, q+1; q >= G + 1 reads 2G - q - 1, 2G - q (the mirror);
+    // q = G straddles the two halves.
+    __device__ static cx<double> pair(const ExecDesc& d, int k, int m, int t)
+    {
         const int lo = (int)d.win_lo[k], hi = (int)d.win_hi[k] + 1;
         const cx<double>* uvm = d.uv + (int64_t)m * (d.G + 1);
         const int G = (int)d.G;
@@ -275,13 +280,69 @@ __device__ __forceinline__ void untangle_at(ZAt Z, int L, int s, cx<T> w, cx<dou
     }
 }
 
+// Column twiddles.  Thread lt of column n2 holds outputs k1 = lt + u sigma
+// (u = F1/16, sigma = 0..15 a permutation of its 16 register slots), which
+// are multiplied by e^{2 pi i n2 k1 / F} = a b^sigma with a = e^{2 pi i n2 lt/F}
+// and b = e^{2 pi i n2 u/F}: two reads of the length-F table per thread, and
+// b^sigma = B^(sigma >> 2) b^(sigma & 3), B = b^4, from a few products (at
+// most six roundings per twiddle).
+template <typename T>
+struct ColTw {
+    cx<T> A[4];  // a B^h
+    cx<T> p[4];  // b^l
+    __device__ __forceinline__ void init(const cx<T>* __restrict__ tw, int F, int n2, int lt, int u)
+    {
+        const int mask = 2 * F - 1;
+        const cx<T> a = ldg(tw + ((2 * n2 * lt) & mask));
+        const cx<T> b = ldg(tw + ((2 * n2 * u) & mask));
+        p[0] = {(T)1, (T)0};
+        p[1] = b;
+        p[2] = cmul(b, b);
+        p[3] = cmul(p[2], b);
+        const cx<T> B = cmul(p[2], p[2]), B2 = cmul(B, B);
+        A[0] = a;
+        A[1] = cmul(a, B);
+        A[2] = cmul(a, B2);
+        A[3] = cmul(A[2], B);
+    }
+};
+
+// Stores the 16 outputs of fft_reg (last radix 2^LR) of column n2, times the
+// column twiddles: slot s holds k1 = lt + u sigma(s).
+template <int LR, typename T, typename StoreF>
+__device__ __forceinline__ void col_store(cx<T> (&v)[16], const ColTw<T>& ct, int lt, int u, int lg2, int n2,
+                                          StoreF store)
+{
+    constexpr int R = 1 << LR;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int sigma = (s >> LR) + ((s & (R - 1)) << (4 - LR));
+        const int k1 = lt + u * sigma;
+        store((k1 << lg2) + n2, cmul(v[s], cmul(ct.A[sigma >> 2], ct.p[sigma & 3])));
+    }
+}
+
+template <typename T, typename StoreF>
+__device__ __forceinline__ void col_store_any(cx<T> (&v)[16], const ColTw<T>& ct, int lt, int lg1, int lg2, int n2,
+                                              StoreF store)
+{
+    const int u = 1 << (lg1 - 4);
+    switch (fft_last_log_radix(lg1)) {
+    case 4: col_store<4>(v, ct, lt, u, lg2, n2, store); break;
+    case 3: col_store<3>(v, ct, lt, u, lg2, n2, store); break;
+    case 2: col_store<2>(v, ct, lt, u, lg2, n2, store); break;
+    default: col_store<1>(v, ct, lt, u, lg2, n2, store); break;
+    }
+}
+
 // Column pass of a power-of-two FFT of length F = F1 F2 (F1 = 2^lg1 <= 2048,
 // F2 = 2^lg2): TC = 2048 / F1 columns per workgroup of 128 threads; thread lt
 // of column c holds n1 = lt + r F1/16.  Output k1 of column n2 is multiplied by
 // e^{2 pi i n2 k1 / F}.  load(t) gives input t = n1 F2 + n2; store(k1 F2 + n2, v).
+// tw: table of length F (column twiddles); tw1: table of length F1 (stages).
 template <typename T, typename LoadF, typename StoreF>
-__device__ __forceinline__ void col_pass(cx<T>* lds, int lg1, int lg2, const cx<T>* __restrict__ tw, int tile,
-                                         LoadF load, StoreF store)
+__device__ __forceinline__ void col_pass(cx<T>* lds, int lg1, int lg2, const cx<T>* __restrict__ tw,
+                                         const cx<T>* __restrict__ tw1, int tile, LoadF load, StoreF store)
 {
     const int F1 = 1 << lg1;
     const int F = 1 << (lg1 + lg2);
@@ -293,23 +354,20 @@ __device__ __forceinline__ void col_pass(cx<T>* lds, int lg1, int lg2, const cx<
     cx<T> v[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = load(((lt + r * step) << lg2) + col);
-    fft_reg<T>(v, lds + c * slice_stride(F1), lg1, lt, true, tw, 2 * F);
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-        const int k1 = fft_out_index(s, lt, lg1);
-        const int q = (2 * col * k1) & (2 * F - 1);  // e^{2 pi i n2 k1 / F} = tw[2 n2 k1 mod 2F]
-        store((k1 << lg2) + col, cmul(v[s], ldg(tw + q)));
-    }
+    ColTw<T> ct;
+    ct.init(tw, F, col, lt, step);
+    fft_reg<T>(v, lds + c * slice_stride(F1), lg1, lt, true, tw1, 2 * F1);
+    col_store_any<T>(v, ct, lt, lg1, lg2, col, store);
 }
 
 // Row pass: TR = max(1, 2048 / F2) rows k1 per workgroup (F2/16 threads each);
 // load(k1 F2 + n2), store(k1 + F1 k2, X) in natural frequency order.
+// tw2: table of length F2 (stages).
 template <typename T, typename LoadF, typename StoreF>
-__device__ __forceinline__ void row_pass(cx<T>* lds, int lg1, int lg2, const cx<T>* __restrict__ tw, int tile,
+__device__ __forceinline__ void row_pass(cx<T>* lds, int lg1, int lg2, const cx<T>* __restrict__ tw2, int tile,
                                          LoadF load, StoreF store)
 {
     const int F2 = 1 << lg2;
-    const int F = 1 << (lg1 + lg2);
     const int ltr = lg2 >= 11 ? 0 : 11 - lg2;  // TR = 2048 / F2 rows
     const int ltp = lg2 - 4;                    // threads per row: F2 / 16
     const int tid = threadIdx.x;
@@ -318,7 +376,7 @@ __device__ __forceinline__ void row_pass(cx<T>* lds, int lg1, int lg2, const cx<
     cx<T> v[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = load((k1 << lg2) + lt + (r << ltp));
-    fft_reg<T>(v, lds + rr * slice_stride(F2), lg2, lt, true, tw, 2 * F);
+    fft_reg<T>(v, lds + rr * slice_stride(F2), lg2, lt, true, tw2, 2 * F2);
 #pragma unroll
     for (int s = 0; s < 16; ++s) store(k1 + (fft_out_index(s, lt, lg2) << lg1), v[s]);
 }
@@ -383,8 +441,53 @@ __global__ void __launch_bounds__(128) k_pass1(const ExecDesc* __restrict__ desc
     const int job = it.a;
     cx<T>* out = reinterpret_cast<cx<T>*>(d.tmp) + (int64_t)job * g.L;
     col_pass<T>(
-        lds, g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw), it.b,
+        lds, g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw), reinterpret_cast<const cx<T>*>(g.tw1), it.b,
         [&](int t) { return to_t<T>(Source<S>::load(d, job, t)); }, [&](int i, cx<T> v) { stg(out + i, v); });
+}
+
+// Column pass of the inverse Hahn blocks, item (desc, term m, column tile).
+// The inputs of term m on block 0's window (which holds every other block's
+// window) are gathered once into registers; each block k then clears what
+// lies outside its own window, transforms, and writes tmp[k M + m].  This
+// reads g and (u_m, v_m) once per term instead of once per (block, term).
+template <typename T>
+__global__ void __launch_bounds__(128) k_pass1_inv(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+    const Item it = items[xcd_item(blockIdx.x, gridDim.x)];
+    const ExecDesc& d = descs[it.desc];
+    const FftGeom& g = geom_of<T>(d);
+    const int m = it.a;
+    const int G = (int)d.G;
+    const int lg1 = g.logL1, lg2 = g.logL2;
+    const int F1 = 1 << lg1, F = 1 << (lg1 + lg2);
+    const int ltc = lg1 >= 11 ? 0 : 11 - lg1;  // TC = 2048 / F1 columns
+    const int tid = threadIdx.x;
+    const int c = tid & ((1 << ltc) - 1), lt = tid >> ltc;
+    const int col = (it.b << ltc) + c;
+    const int step = F1 >> 4;
+    const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
+    cx<T>* slice = lds + c * slice_stride(F1);
+    const cx<T>* tw1 = reinterpret_cast<const cx<T>*>(g.tw1);
+    cx<T> z[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) z[r] = to_t<T>(Source<Src::InvAsy>::pair(d, 0, m, ((lt + r * step) << lg2) + col));
+    ColTw<T> ct;
+    ct.init(tw, F, col, lt, step);
+    for (int k = 0; k < d.nblk; ++k) {
+        const int lo = (int)d.win_lo[k], hi = (int)d.win_hi[k] + 1;
+        cx<T> v[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int q = 2 * (((lt + r * step) << lg2) + col);
+            const int j0 = q <= G ? q : 2 * G - q, j1 = q + 1 <= G ? q + 1 : 2 * G - q - 1;
+            v[r] = {in_range(j0, lo, hi) ? z[r].re : (T)0, in_range(j1, lo, hi) ? z[r].im : (T)0};
+        }
+        fft_reg<T>(v, slice, lg1, lt, true, tw1, 2 * F1);
+        cx<T>* out = reinterpret_cast<cx<T>*>(d.tmp) + (int64_t)(k * d.M + m) * g.L;
+        col_store_any<T>(v, ct, lt, lg1, lg2, col, [&](int i, cx<T> x) { stg(out + i, x); });
+    }
 }
 
 // Row pass, item (desc, unit tile): TU units per workgroup; unit u holds rows
@@ -428,7 +531,7 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = ldg(in + lt + r * tpr);
         cx<T>* slice = buf + rs * sst;
-        fft_reg<T>(v, slice, g.logL2, lt, true, tw, 2 * L);
+        fft_reg<T>(v, slice, g.logL2, lt, true, reinterpret_cast<const cx<T>*>(g.tw2), 2 * L2);
 #pragma unroll
         for (int s = 0; s < 16; ++s) slice[lds_pad(fft_out_index(s, lt, g.logL2))] = v[s];
         __syncthreads();
@@ -517,7 +620,8 @@ __global__ void __launch_bounds__(128) k_bs_col1(const ExecDesc* __restrict__ de
     const cx<T>* chirp = reinterpret_cast<const cx<T>*>(g.chirp);
     cx<T>* base = bs_job<T>(d, g, job);
     col_pass<T>(
-        reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw), it.b,
+        reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw),
+        reinterpret_cast<const cx<T>*>(g.tw1), it.b,
         [&](int t) {
             return t < L ? cmul(to_t<T>(Source<S>::load(d, job, t)), ldg(chirp + t)) : cx<T>{(T)0, (T)0};
         },
@@ -535,7 +639,7 @@ __global__ void __launch_bounds__(256) k_bs_row1(const ExecDesc* __restrict__ de
     cx<T>* base = bs_job<T>(d, g, it.a);
     const int P = (int)g.P;
     row_pass<T>(
-        reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw), it.b,
+        reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw2), it.b,
         [&](int i) { return ldg(base + i); }, [&](int i, cx<T> v) { stg(base + P + i, v); });
 }
 
@@ -551,7 +655,8 @@ __global__ void __launch_bounds__(128) k_bs_col2(const ExecDesc* __restrict__ de
     const int P = (int)g.P;
     const cx<T>* bl = reinterpret_cast<const cx<T>*>(g.bl);
     col_pass<T>(
-        reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw), it.b,
+        reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw),
+        reinterpret_cast<const cx<T>*>(g.tw1), it.b,
         [&](int t) { return conj(cmul(ldg(base + P + t), ldg(bl + t))); }, [&](int i, cx<T> v) { stg(base + i, v); });
 }
 
@@ -568,7 +673,7 @@ __global__ void __launch_bounds__(256) k_bs_row2(const ExecDesc* __restrict__ de
     const cx<T>* chirp = reinterpret_cast<const cx<T>*>(g.chirp);
     const T invP = (T)1 / (T)P;
     row_pass<T>(
-        reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw), it.b,
+        reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw2), it.b,
         [&](int i) { return ldg(base + i); },
         [&](int s, cx<T> v) {
             if (s < L) stg(base + P + s, cmul(ldg(chirp + s), cscale(conj(v), invP)));
@@ -802,6 +907,9 @@ cjt_status run(const Launch& L, const ExecDesc* dd, const Item* it, hipStream_t 
     switch (L.kind) {
     case Kind::FftSingle: return go(k_single<T, S, K>, L, s, dd, it, L.acc_off);
     case Kind::FftPass1: return go(k_pass1<T, S>, L, s, dd, it);
+    case Kind::FftPass1Inv:
+        if constexpr (S == Src::InvAsy) return go(k_pass1_inv<T>, L, s, dd, it);
+        return fail(CJT_EINVAL, "multi-block column pass is for the inverse Hahn blocks");
     case Kind::FftPass2: return go(k_pass2<T, K, kMulti>, L, s, dd, it, L.acc_off);
     case Kind::BsSingle: return go(k_bs_single<T, S, K>, L, s, dd, it, L.acc_off);
     case Kind::BsCol1: return go(k_bs_col1<T, S>, L, s, dd, it);
@@ -899,9 +1007,15 @@ cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sin
             const int TC = g.L1 >= 2048 ? 1 : 2048 / g.L1;
             const int TU = g.L2 >= 1024 ? 1 : 1024 / g.L2;
             const int nth2 = 2 * TU * (g.L2 / 16);
-            Bucket& b1 = bucket(Kind::FftPass1, 128, name_cols);
-            for (int t = 0; t < g.L2 / TC; ++t)
-                for (int it = 0; it < jobs; ++it) b1.items.push_back(Item{i, job_at(d, it, multi), t, 0});
+            const bool inv = src == Src::InvAsy;
+            Bucket& b1 = bucket(inv ? Kind::FftPass1Inv : Kind::FftPass1, 128, name_cols);
+            for (int t = 0; t < g.L2 / TC; ++t) {
+                if (inv) {  // one item per term: all blocks of the term in the workgroup
+                    for (int m = 0; m < d.M; ++m) b1.items.push_back(Item{i, m, t, 0});
+                } else {
+                    for (int it = 0; it < jobs; ++it) b1.items.push_back(Item{i, job_at(d, it, multi), t, 0});
+                }
+            }
             b1.lds = std::max(b1.lds, (size_t)TC * slice_stride(g.L1) * esz);
             b1.flops += 0.5 * fl;
             b1.bytes += 0.5 * by;
@@ -966,9 +1080,9 @@ cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sin
         return intern(std::string(nm) + sfx);
     };
     // launch order: single-workgroup kinds, then the two-pass chains in dependency order
-    const Kind order[] = {Kind::FftSingle, Kind::BsSingle, Kind::FftJobs, Kind::BsJobs,     Kind::JobReduce,
-                          Kind::FftPass1,  Kind::FftPass2, Kind::BsCol1,  Kind::BsRow1,     Kind::BsCol2,
-                          Kind::BsRow2,    Kind::BsUntangle};
+    const Kind order[] = {Kind::FftSingle, Kind::BsSingle, Kind::FftJobs, Kind::BsJobs,  Kind::JobReduce,
+                          Kind::FftPass1,  Kind::FftPass1Inv, Kind::FftPass2, Kind::BsCol1, Kind::BsRow1,
+                          Kind::BsCol2,    Kind::BsRow2,      Kind::BsUntangle};
     for (Kind k : order) {
         for (auto& b : bk) {
             if (b.kind != k || b.items.empty()) continue;
@@ -1077,14 +1191,14 @@ __global__ void __launch_bounds__(128) k_bl_col(FftGeom g, cx<double>* scratch)
     const int64_t P = g.P, L = g.L;
     col_pass<double>(
         reinterpret_cast<cx<double>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<double>*>(g.tw),
-        blockIdx.x, [&](int64_t t) { return bl_input(chirp, L, P, t); }, [&](int64_t i, cx<double> v) { scratch[i] = v; });
+        reinterpret_cast<const cx<double>*>(g.tw1), blockIdx.x, [&](int64_t t) { return bl_input(chirp, L, P, t); }, [&](int64_t i, cx<double> v) { scratch[i] = v; });
 }
 
 __global__ void __launch_bounds__(256) k_bl_row(FftGeom g, const cx<double>* scratch, cx<double>* bl)
 {
     extern __shared__ unsigned char smem_raw[];
     row_pass<double>(
-        reinterpret_cast<cx<double>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<double>*>(g.tw),
+        reinterpret_cast<cx<double>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<double>*>(g.tw2),
         blockIdx.x, [&](int64_t i) { return scratch[i]; }, [&](int64_t i, cx<double> v) { bl[i] = v; });
 }
 
@@ -1110,6 +1224,10 @@ cjt_status make_chirp_tables(FftGeom* g, bool fp32, hipStream_t st)
         s = fft_twiddles_cached(P, false, st, &tw64);
         if (s != CJT_OK) return s;
         g64.tw = tw64;
+        if (!g->single) {
+            if ((s = fft_twiddles_cached(g->L1, false, st, &g64.tw1)) != CJT_OK) return s;
+            if ((s = fft_twiddles_cached(g->L2, false, st, &g64.tw2)) != CJT_OK) return s;
+        }
     }
     if (g->single) {
         const size_t lds = lds_bytes(P, sizeof(cx<double>));
