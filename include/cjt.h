@@ -50,14 +50,18 @@ typedef enum {
     CJT_ENOMEM = 3,      /* device or host allocation failed */
     CJT_EDEVICE = 4,     /* a HIP call failed */
     CJT_EBUSY = 5,       /* resource in use */
-    CJT_EUNSUPPORTED = 6 /* valid request this build does not implement */
+    CJT_EUNSUPPORTED = 6, /* valid request this build does not implement */
+    CJT_ECANCELED = 7     /* serving: the request was cancelled before it ran */
 } cjt_status;
 
 /* Plan flags. */
 enum {
     CJT_FP64 = 0,          /* every step in FP64 */
-    CJT_FP32_BULK = 1      /* the DCT-I/DST-I of the Hahn blocks in FP32 with FP32 accumulation;
+    CJT_FP32_BULK = 1,     /* the DCT-I/DST-I of the Hahn blocks in FP32 with FP32 accumulation;
                               diagonals, recurrences and boundary DCTs stay FP64 */
+    CJT_BATCH_INVARIANT = 8 /* results of this plan are bitwise the same whatever else shares a
+                              batched call: its recurrence segments are sized from its own
+                              degree alone instead of from the whole batch */
 };
 
 /* Direction flags of a persistent batch. */
@@ -105,7 +109,7 @@ typedef struct {
  * parameters (alpha, beta) in (-1/2, 1/2]
  * (Sec. 2.1: Hahn's remainder bound), and M Hahn terms (0 = chosen by the
  * library's cost model, else 2 <= M <= 30; Sec. 2.2 needs M >= 2).  flags is
- * CJT_FP64 or CJT_FP32_BULK.  Plan arrays are computed on the device on
+ * CJT_FP64 or CJT_FP32_BULK, optionally or-ed with CJT_BATCH_INVARIANT.  Plan arrays are computed on the device on
  * `stream`; the call returns after they are complete.  *out receives the plan. */
 cjt_status cjt_plan(cjt_plan_t* out, int64_t N, double alpha, double beta, int M, unsigned flags,
                     void* stream);
@@ -156,6 +160,91 @@ cjt_status cjt_batch_execute(cjt_batch_t batch, const double* d_in, double* d_ou
 cjt_status cjt_batch_query(cjt_batch_t batch, cjt_batch_info* out);
 /* Release a batch (waits for the device). NULL is accepted. */
 cjt_status cjt_batch_destroy(cjt_batch_t batch);
+
+/* ------------------------------------------------------------------ serving
+ *
+ * A transform server (Sec. 4: plans made once and reused for many sets of
+ * coefficients) for a stream of independent requests of any degree,
+ * direction and parameters, on one device.  A batcher thread takes the
+ * queued requests of one direction and precision (oldest first, at most
+ * max_batch) and issues them as one batched call while earlier calls still
+ * run (continuous batching: at most max_inflight calls queued on the device);
+ * a completion thread stamps each request's latency (arrival to completion of
+ * its call, host clock) when the call's event completes.
+ *
+ * Memory: the server allocates its whole HBM budget once at creation and
+ * never more.  It holds the execution workspace (workspace_bytes), the
+ * descriptor buffers of the calls in flight, and resident plans keyed by
+ * (N, alpha, beta, precision), least recently used first out when a new plan
+ * does not fit; a plan used by a queued or running call is never evicted.
+ * A request whose plan or workspace cannot fit even in an empty server fails
+ * with CJT_ENOMEM; one that waits for memory held by running calls is
+ * admitted when they complete.  The power-of-two FFT twiddle tables are
+ * shared library-wide and are not part of the budget.
+ *
+ * Requests: flags = CJT_DIR_FWD or CJT_DIR_INV, optionally | CJT_FP32_BULK;
+ * d_in / d_out are device buffers of N + 1 doubles that stay valid and
+ * untouched until the request completes, and d_in must be ready when the
+ * request is submitted.  Server plans are made with CJT_BATCH_INVARIANT, so a
+ * result is bitwise the result of the same request executed alone with such
+ * a plan, whatever it was batched with. */
+typedef struct cjt_server_s* cjt_server_t;
+
+typedef struct {
+    size_t hbm_budget;        /* device bytes the server may hold (required) */
+    size_t workspace_bytes;   /* part of the budget for execution intermediates (0: a quarter) */
+    int32_t max_batch;        /* requests per batched call (0: 256) */
+    int32_t max_inflight;     /* batched calls queued on the device at once (0: 2) */
+    int32_t M;                /* Hahn terms of new plans (0: the cost model's choice) */
+    int32_t start_paused;     /* 1: the batcher takes no request until cjt_server_pause(s, 0) */
+} cjt_server_config;
+
+typedef struct {
+    int64_t submitted, completed, failed, cancelled;
+    int64_t batches;              /* batched calls issued */
+    double mean_batch;            /* requests per batched call */
+    int64_t plan_hits, plan_misses, plan_evictions;
+    int64_t admission_stalls;     /* times the batcher waited for memory held by running calls */
+    int64_t plans_resident;
+    size_t plan_bytes;            /* device bytes of resident plans */
+    size_t budget_bytes;          /* the server's allocation (= hbm_budget) */
+    size_t peak_used_bytes;       /* high-water mark of budget bytes in use */
+    int64_t lat_count;            /* completed requests since the last reset */
+    double lat_p50_us, lat_p99_us, lat_mean_us, lat_max_us;
+} cjt_server_stats;
+
+/* Create a server on the current device; allocates the budget.  CJT_EINVAL
+ * if the budget cannot hold the workspace and descriptor buffers. */
+cjt_status cjt_server_create(cjt_server_t* out, const cjt_server_config* cfg);
+/* Queue one request (arrival = now).  Argument errors return synchronously
+ * and queue nothing; *ticket identifies the request. */
+cjt_status cjt_server_submit(cjt_server_t s, unsigned flags, int64_t N, double alpha, double beta,
+                             const double* d_in, double* d_out, int64_t* ticket);
+/* Load generator: submits request i (host arrays of `count` entries) at
+ * arrival_us[i] microseconds after the call starts (non-decreasing), waiting
+ * on the host clock in between; latency counts from that scheduled arrival.
+ * Returns after the last submission.  A request with bad arguments gets
+ * ticket -1 and is counted as failed. */
+cjt_status cjt_server_replay(cjt_server_t s, int64_t count, const unsigned* flags, const int64_t* N,
+                             const double* alpha, const double* beta, const double* const* d_in,
+                             double* const* d_out, const double* arrival_us, int64_t* tickets);
+/* Block until the request completes; *result receives its status (CJT_OK,
+ * CJT_ENOMEM, CJT_EDEVICE, CJT_ECANCELED, ...), *latency_us its latency
+ * (either may be NULL).  The ticket is then forgotten. */
+cjt_status cjt_server_wait(cjt_server_t s, int64_t ticket, cjt_status* result, double* latency_us);
+/* Cancel a request still in the queue: CJT_OK (its result becomes
+ * CJT_ECANCELED), CJT_EBUSY if it was already taken into a call. */
+cjt_status cjt_server_cancel(cjt_server_t s, int64_t ticket);
+/* Stop (1) or resume (0) taking requests from the queue. */
+cjt_status cjt_server_pause(cjt_server_t s, int paused);
+/* Block until every submitted request has completed (not while paused with
+ * requests queued: returns CJT_EBUSY then). */
+cjt_status cjt_server_drain(cjt_server_t s);
+/* Counters and latency percentiles; reset != 0 clears the latency record
+ * and the counters after reading. */
+cjt_status cjt_server_query(cjt_server_t s, cjt_server_stats* out, int reset);
+/* Drain, stop the threads and release everything. NULL is accepted. */
+cjt_status cjt_server_destroy(cjt_server_t s);
 
 /* Describe a plan (host memory out). */
 cjt_status cjt_plan_query(cjt_plan_t plan, cjt_plan_info* out);

@@ -15,9 +15,10 @@ import threading
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcjt_hip.so")
 
-CJT_OK, CJT_EINVAL, CJT_EDOMAIN, CJT_ENOMEM, CJT_EDEVICE, CJT_EBUSY, CJT_EUNSUPPORTED = range(7)
+CJT_OK, CJT_EINVAL, CJT_EDOMAIN, CJT_ENOMEM, CJT_EDEVICE, CJT_EBUSY, CJT_EUNSUPPORTED, CJT_ECANCELED = range(8)
 CJT_FP64 = 0
 CJT_FP32_BULK = 1
+CJT_BATCH_INVARIANT = 8
 CJT_DIR_FWD = 2
 CJT_DIR_INV = 4
 CJT_MAX_BLOCKS = 16
@@ -27,6 +28,8 @@ _EXPORTS = (
     "cjt_plan_query", "cjt_plan_describe", "cjt_plan_destroy", "cjt_strerror", "cjt_last_error",
     "cjt_version", "cjt_profile_enable", "cjt_profile_collect",
     "cjt_batch_create", "cjt_batch_execute", "cjt_batch_query", "cjt_batch_destroy",
+    "cjt_server_create", "cjt_server_submit", "cjt_server_replay", "cjt_server_wait", "cjt_server_cancel",
+    "cjt_server_pause", "cjt_server_drain", "cjt_server_query", "cjt_server_destroy",
 )
 
 
@@ -89,6 +92,44 @@ class cjt_batch_info(ctypes.Structure):
     ]
 
 
+class cjt_server_config(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget", ctypes.c_size_t),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("max_batch", ctypes.c_int32),
+        ("max_inflight", ctypes.c_int32),
+        ("M", ctypes.c_int32),
+        ("start_paused", ctypes.c_int32),
+    ]
+
+
+class cjt_server_stats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64),
+        ("completed", ctypes.c_int64),
+        ("failed", ctypes.c_int64),
+        ("cancelled", ctypes.c_int64),
+        ("batches", ctypes.c_int64),
+        ("mean_batch", ctypes.c_double),
+        ("plan_hits", ctypes.c_int64),
+        ("plan_misses", ctypes.c_int64),
+        ("plan_evictions", ctypes.c_int64),
+        ("admission_stalls", ctypes.c_int64),
+        ("plans_resident", ctypes.c_int64),
+        ("plan_bytes", ctypes.c_size_t),
+        ("budget_bytes", ctypes.c_size_t),
+        ("peak_used_bytes", ctypes.c_size_t),
+        ("lat_count", ctypes.c_int64),
+        ("lat_p50_us", ctypes.c_double),
+        ("lat_p99_us", ctypes.c_double),
+        ("lat_mean_us", ctypes.c_double),
+        ("lat_max_us", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class CJTError(RuntimeError):
     def __init__(self, status, what):
         self.status = status
@@ -132,9 +173,20 @@ def load(path=LIB_PATH):
         lib.cjt_batch_execute.argtypes = [vp, vp, vp, vp]
         lib.cjt_batch_query.argtypes = [vp, P(cjt_batch_info)]
         lib.cjt_batch_destroy.argtypes = [vp]
+        lib.cjt_server_create.argtypes = [P(vp), P(cjt_server_config)]
+        lib.cjt_server_submit.argtypes = [vp, cu, i64, dbl, dbl, vp, vp, P(i64)]
+        lib.cjt_server_replay.argtypes = [vp, i64, P(cu), P(i64), P(dbl), P(dbl), P(vp), P(vp), P(dbl), P(i64)]
+        lib.cjt_server_wait.argtypes = [vp, i64, P(ci), P(dbl)]
+        lib.cjt_server_cancel.argtypes = [vp, i64]
+        lib.cjt_server_pause.argtypes = [vp, ci]
+        lib.cjt_server_drain.argtypes = [vp]
+        lib.cjt_server_query.argtypes = [vp, P(cjt_server_stats), ci]
+        lib.cjt_server_destroy.argtypes = [vp]
         for f in ("cjt_plan", "cjt_forward", "cjt_inverse", "cjt_forward_batched", "cjt_inverse_batched",
                   "cjt_plan_query", "cjt_plan_describe", "cjt_plan_destroy", "cjt_batch_create",
-                  "cjt_batch_execute", "cjt_batch_query", "cjt_batch_destroy"):
+                  "cjt_batch_execute", "cjt_batch_query", "cjt_batch_destroy", "cjt_server_create",
+                  "cjt_server_submit", "cjt_server_replay", "cjt_server_wait", "cjt_server_cancel",
+                  "cjt_server_pause", "cjt_server_drain", "cjt_server_query", "cjt_server_destroy"):
             getattr(lib, f).restype = ci
         _lib = lib
         return lib
@@ -281,6 +333,101 @@ def cjt_batch_query(batch):
 
 def cjt_batch_destroy(batch):
     batch.destroy()
+
+
+class Server:
+    """Owning wrapper of a cjt_server_t (continuous-batching transform server)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def destroy(self):
+        if self.handle:
+            h, self.handle = self.handle, None
+            load().cjt_server_destroy(h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def submit(self, flags, N, alpha, beta, d_in, d_out):
+        return cjt_server_submit(self, flags, N, alpha, beta, d_in, d_out)
+
+    def wait(self, ticket):
+        return cjt_server_wait(self, ticket)
+
+    def stats(self, reset=False):
+        return cjt_server_query(self, reset)
+
+
+def cjt_server_create(hbm_budget, workspace_bytes=0, max_batch=0, max_inflight=0, M=0, start_paused=False):
+    cfg = cjt_server_config(int(hbm_budget), int(workspace_bytes), int(max_batch), int(max_inflight), int(M),
+                            1 if start_paused else 0)
+    h = ctypes.c_void_p()
+    _check(load().cjt_server_create(ctypes.byref(h), ctypes.byref(cfg)), "cjt_server_create")
+    return Server(h.value)
+
+
+def cjt_server_submit(server, flags, N, alpha, beta, d_in, d_out):
+    """Queue one request; returns its ticket.  d_in must be ready (synchronise its producer first)."""
+    t = ctypes.c_int64(-1)
+    _check(load().cjt_server_submit(server.handle, int(flags), int(N), float(alpha), float(beta), _ptr(d_in),
+                                    _ptr(d_out), ctypes.byref(t)), "cjt_server_submit")
+    return t.value
+
+
+def cjt_server_replay(server, flags, N, alpha, beta, d_in, d_out, arrival_us):
+    """Submit request i at arrival_us[i] microseconds after the call starts; returns the tickets."""
+    n = len(flags)
+    A = lambda ct, xs: (ct * max(n, 1))(*xs)
+    tickets = (ctypes.c_int64 * max(n, 1))()
+    _check(load().cjt_server_replay(server.handle, n, A(ctypes.c_uint, [int(f) for f in flags]),
+                                    A(ctypes.c_int64, [int(x) for x in N]), A(ctypes.c_double, [float(x) for x in alpha]),
+                                    A(ctypes.c_double, [float(x) for x in beta]),
+                                    A(ctypes.c_void_p, [_ptr(x) for x in d_in]),
+                                    A(ctypes.c_void_p, [_ptr(x) for x in d_out]),
+                                    A(ctypes.c_double, [float(x) for x in arrival_us]), tickets),
+           "cjt_server_replay")
+    return [tickets[i] for i in range(n)]
+
+
+def cjt_server_wait(server, ticket):
+    """Block until the request completes; returns (status, latency_us)."""
+    st = ctypes.c_int(0)
+    lat = ctypes.c_double(0.0)
+    _check(load().cjt_server_wait(server.handle, int(ticket), ctypes.byref(st), ctypes.byref(lat)), "cjt_server_wait")
+    return st.value, lat.value
+
+
+def cjt_server_cancel(server, ticket):
+    """Returns the status: CJT_OK if cancelled, CJT_EBUSY if already running."""
+    return int(load().cjt_server_cancel(server.handle, int(ticket)))
+
+
+def cjt_server_pause(server, paused=True):
+    _check(load().cjt_server_pause(server.handle, 1 if paused else 0), "cjt_server_pause")
+
+
+def cjt_server_drain(server):
+    _check(load().cjt_server_drain(server.handle), "cjt_server_drain")
+
+
+def cjt_server_query(server, reset=False):
+    out = cjt_server_stats()
+    _check(load().cjt_server_query(server.handle, ctypes.byref(out), 1 if reset else 0), "cjt_server_query")
+    return out
+
+
+def cjt_server_destroy(server):
+    server.destroy()
 
 
 def cjt_plan_query(plan):

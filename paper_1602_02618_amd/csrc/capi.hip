@@ -18,9 +18,6 @@
 #include "exec.h"
 #include "plan.h"
 
-struct cjt_plan_s {
-    cjt::Plan p;
-};
 
 // A persistent batch: the launch program, its descriptors and work items
 // resident on the device, and its own workspace; executing it only launches
@@ -185,8 +182,6 @@ cjt_status check_batch(const std::vector<const Plan*>& plans)
     return CJT_OK;
 }
 
-// One-shot execution: program built per call, descriptors and items uploaded
-// through the stream's pinned staging buffer, workspace kept per stream.
 cjt_status execute(bool inverse, const std::vector<const Plan*>& plans, const std::vector<int64_t>& io_off,
                    const double* in, double* out, hipStream_t st)
 {
@@ -235,17 +230,6 @@ void fill_part_info(const Part& p, cjt_partition_info* o)
     o->rec_entries = p.rec_entries;
 }
 
-cjt_status check_args(int64_t N, double alpha, double beta, int M, unsigned flags)
-{
-    if (N < 1) return fail(CJT_EINVAL, "N must be >= 1");
-    if (N > kMaxN) return fail(CJT_EUNSUPPORTED, "N above 2^21 is not supported");
-    if (!isfinite(alpha) || !isfinite(beta) || !(alpha > -0.5 && alpha <= 0.5) || !(beta > -0.5 && beta <= 0.5))
-        return fail(CJT_EDOMAIN, "alpha and beta must lie in (-1/2, 1/2]");
-    if (M != 0 && (M < 2 || M > kMaxM)) return fail(CJT_EDOMAIN, "M must be 0 (auto) or in [2, 30]");
-    if (flags & ~(unsigned)CJT_FP32_BULK) return fail(CJT_EINVAL, "unknown flag");
-    return CJT_OK;
-}
-
 void describe(const Plan& P, cjt_plan_info* out)
 {
     memset(out, 0, sizeof(*out));
@@ -264,6 +248,19 @@ void describe(const Plan& P, cjt_plan_info* out)
     out->device_bytes = P.arena_bytes;
 }
 
+}  // namespace
+
+cjt_status check_args(int64_t N, double alpha, double beta, int M, unsigned flags)
+{
+    if (N < 1) return fail(CJT_EINVAL, "N must be >= 1");
+    if (N > kMaxN) return fail(CJT_EUNSUPPORTED, "N above 2^21 is not supported");
+    if (!isfinite(alpha) || !isfinite(beta) || !(alpha > -0.5 && alpha <= 0.5) || !(beta > -0.5 && beta <= 0.5))
+        return fail(CJT_EDOMAIN, "alpha and beta must lie in (-1/2, 1/2]");
+    if (M != 0 && (M < 2 || M > kMaxM)) return fail(CJT_EDOMAIN, "M must be 0 (auto) or in [2, 30]");
+    if (flags & ~(unsigned)(CJT_FP32_BULK | CJT_BATCH_INVARIANT)) return fail(CJT_EINVAL, "unknown flag");
+    return CJT_OK;
+}
+
 void plan_host(Plan* P, int64_t N, double alpha, double beta, int M, unsigned flags)
 {
     P->N = N;
@@ -273,9 +270,8 @@ void plan_host(Plan* P, int64_t N, double alpha, double beta, int M, unsigned fl
     choose_partitions(N, alpha, beta, M, &P->fwd, &P->inv);
     build_tasks(P->fwd, kRecWidthFwd, &P->tasks_f, &P->part_total_f);
     build_tasks(P->inv, kRecWidthInv, &P->tasks_i, &P->part_total_i);
+    plan_layout(P);
 }
-
-}  // namespace
 
 }  // namespace cjt
 
@@ -293,6 +289,7 @@ const char* cjt_strerror(cjt_status s)
         case CJT_EDEVICE: return "HIP runtime error";
         case CJT_EBUSY: return "resource busy";
         case CJT_EUNSUPPORTED: return "not supported by this build";
+        case CJT_ECANCELED: return "request cancelled";
     }
     return "unknown status";
 }
@@ -349,12 +346,6 @@ cjt_status cjt_plan_describe(int64_t N, double alpha, double beta, int M, unsign
     Plan P;
     plan_host(&P, N, alpha, beta, M, flags);
     describe(P, out);
-    // estimate of the device arena
-    const int64_t nf = N + 1, ni = 2 * N + 1;
-    const int Mx = out->M;
-    out->device_bytes = sizeof(double) * (size_t)Mx * nf + 16 * (size_t)P.fwd.M * nf + 16 * (size_t)P.inv.M * ni +
-                        8 * (size_t)ni * 2 + 8 * (size_t)nf + 32 * 6 * (size_t)nf +
-                        sizeof(RecTask) * (P.tasks_f.size() + P.tasks_i.size());
     return CJT_OK;
 }
 
@@ -371,9 +362,8 @@ cjt_status cjt_plan(cjt_plan_t* out, int64_t N, double alpha, double beta, int M
         delete h;
         return fail(CJT_EDEVICE, "no HIP device");
     }
-    s = build_plan_device(&h->p, (hipStream_t)stream);
+    s = build_plan_device(&h->p, (hipStream_t)stream, nullptr, nullptr);
     if (s != CJT_OK) {
-        if (h->p.arena) (void)hipFree(h->p.arena);
         delete h;
         return s;
     }
@@ -384,7 +374,7 @@ cjt_status cjt_plan(cjt_plan_t* out, int64_t N, double alpha, double beta, int M
 cjt_status cjt_plan_destroy(cjt_plan_t plan)
 {
     if (!plan) return CJT_OK;
-    if (plan->p.arena) {
+    if (plan->p.arena && plan->p.own_arena) {
         CJT_HIP_TRY(hipDeviceSynchronize());
         CJT_HIP_TRY(hipFree(plan->p.arena));
     }

@@ -68,7 +68,7 @@ struct ExecDesc {
     int32_t M;          // Hahn terms
     int32_t nblk;       // Hahn blocks
     int32_t ntasks;     // recurrence tasks
-    int32_t pad0;
+    int32_t rec_seg;    // recurrence segment length: tasks with more than 2 rec_seg degrees are split
     int64_t deg_lo[kMaxBlocks], deg_hi[kMaxBlocks];  // half-open degree ranges of the blocks
     int64_t win_lo[kMaxBlocks], win_hi[kMaxBlocks];  // inclusive grid windows of the blocks
     const double* C;          // [M][N+1]   Hahn coefficients C_{n,m}
@@ -268,21 +268,26 @@ cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sin
 // Intermediate bytes one instance needs for a pass of `jobs` jobs over the
 // length of geometry g (0: none), in the mode add_fft will choose.
 size_t fft_tmp_bytes(const FftGeom& g, int64_t jobs, bool fp32, bool job_parallel);
-// Recurrence launches over all instances; the segment length `seg` splits
-// tasks whose degree range exceeds 2*seg.  Returns the segment-record
-// doubles each instance needs (rec_seg_doubles) before the seg pointers are set.
-int32_t rec_segment_length(const Program& pr, const std::vector<const RecTask*>& tasks);
-int64_t rec_seg_doubles(const ExecDesc& d, const RecTask* tasks, int32_t seg);
-void add_rec_fwd(Program& pr, const std::vector<const RecTask*>& tasks, int32_t seg, int stream, double flops,
-                 double bytes);
-void add_rec_inv(Program& pr, const std::vector<const RecTask*>& tasks, int32_t seg, int stream, double flops,
-                 double bytes);
+// Recurrence launches over all instances.  Each descriptor's rec_seg splits
+// its tasks longer than 2 rec_seg degrees.  rec_segment_length picks it from
+// the total work of `which` instances (all of them: the whole call; one: an
+// instance alone, for results that do not depend on the rest of the call);
+// rec_seg_doubles gives the segment-record doubles an instance then needs.
+int32_t rec_segment_length(const Program& pr, const std::vector<const RecTask*>& tasks, const std::vector<int>& which);
+int64_t rec_seg_doubles(const ExecDesc& d, const RecTask* tasks);
+void add_rec_fwd(Program& pr, const std::vector<const RecTask*>& tasks, int stream, double flops, double bytes);
+void add_rec_inv(Program& pr, const std::vector<const RecTask*>& tasks, int stream, double flops, double bytes);
 void add_rec_inv_reduce(Program& pr, int stream, double bytes);
 
 cjt_status launch_fft(const Launch& L, const ExecDesc* d_desc, const Item* d_items, hipStream_t s);
 cjt_status launch_rec(const Launch& L, const ExecDesc* d_desc, const Item* d_items, hipStream_t s);
 cjt_status make_twiddles(int64_t L, bool fp32, const void** out, hipStream_t stream);
 cjt_status fft_twiddles_cached(int64_t L, bool fp32, hipStream_t st, const void** out);
-cjt_status make_chirp_tables(FftGeom* g, bool fp32, hipStream_t st);
+// Chirp-z tables of a non-power-of-two geometry: device bytes they occupy,
+// scratch bytes their construction needs, and the construction itself into
+// caller memory (owned by the plan of that length).
+size_t chirp_table_bytes(const FftGeom& g, bool fp32);
+size_t chirp_scratch_bytes(const FftGeom& g, bool fp32);
+cjt_status make_chirp_tables(FftGeom* g, bool fp32, hipStream_t st, char* mem, char* scratch);
 
 }  // namespace cjt

@@ -7,6 +7,11 @@
 #include "cjt_internal.h"
 #include "plan.h"
 
+// Handle behind cjt_plan_t.
+struct cjt_plan_s {
+    cjt::Plan p;
+};
+
 namespace cjt {
 
 // Where an instance's scratch lives, as byte offsets into the workspace

@@ -63,7 +63,7 @@ __global__ void k_patch(ExecDesc* __restrict__ descs, int count, const double* i
 }  // namespace
 
 cjt_status build_program(const std::vector<const Plan*>& plans, const std::vector<int64_t>& io_off, bool inverse,
-                         size_t tmp_limit, bool with_patch, hipStream_t st0, Built* out)
+                         size_t tmp_limit, bool with_patch, hipStream_t, Built* out)
 {
     Built& b = *out;
     b = Built{};
@@ -103,10 +103,8 @@ cjt_status build_program(const std::vector<const Plan*>& plans, const std::vecto
         d.recp = inverse ? P.ip : P.fp;
         d.recm = inverse ? P.im : P.fm;
         d.io_off = io_off[i];
-        cjt_status s = fft_geometry(d.G, false, st0, &d.geo);
-        if (s != CJT_OK) return s;
-        d.geob = d.geo;
-        if (fp32 && (s = fft_geometry(d.G, true, st0, &d.geob)) != CJT_OK) return s;
+        d.geo = inverse ? P.geo_i : P.geo_f;
+        d.geob = fp32 ? (inverse ? P.geob_i : P.geob_f) : d.geo;
         pr.descs[i] = d;
         tasks[i] = inverse ? P.tasks_i.data() : P.tasks_f.data();
         const Work w = work_of(P, inverse);
@@ -118,7 +116,16 @@ cjt_status build_program(const std::vector<const Plan*>& plans, const std::vecto
         rec_b += w.rec_bytes;
         red_b += 16.0 * (double)(P.N + 1);
     }
-    const int32_t S = rec_segment_length(pr, tasks);
+    // recurrence segment length: from the whole call, or per instance for
+    // plans that ask for results independent of the rest of the call
+    {
+        std::vector<int> all(n);
+        for (size_t i = 0; i < n; ++i) all[i] = (int)i;
+        const int32_t S = rec_segment_length(pr, tasks, all);
+        for (size_t i = 0; i < n; ++i)
+            pr.descs[i].rec_seg =
+                (plans[i]->flags & CJT_BATCH_INVARIANT) ? rec_segment_length(pr, tasks, std::vector<int>{(int)i}) : S;
+    }
     // few instances: spread the Hahn jobs of single-workgroup lengths over workgroups
     const bool job_parallel = n <= kJobParallelMax;
 
@@ -143,7 +150,7 @@ cjt_status build_program(const std::vector<const Plan*>& plans, const std::vecto
             o.part = off;
             off += a256(sizeof(double) * (size_t)std::max<int64_t>(1, P.part_total_i));
         }
-        const int64_t segd = rec_seg_doubles(d, tasks[i], S);
+        const int64_t segd = rec_seg_doubles(d, tasks[i]);
         o.seg = SIZE_MAX;
         if (segd > 0) {
             o.seg = off;
@@ -189,7 +196,7 @@ cjt_status build_program(const std::vector<const Plan*>& plans, const std::vecto
     cjt_status s = CJT_OK;
     if (!inverse) {
         mark(Kind::Fork);
-        add_rec_fwd(pr, tasks, S, 1, rec_f, rec_b);
+        add_rec_fwd(pr, tasks, 1, rec_f, rec_b);
         for (auto& c : chunks)
             if ((s = add_fft(pr, c, Src::FwdAsy, Sink::FwdAsy, fp32, 0, fp32 ? "hahn_fwd_cols_fp32" : "hahn_fwd_cols",
                              fp32 ? "hahn_fwd_rows_fp32" : "hahn_fwd_rows", asy_f, asy_b, job_parallel)) != CJT_OK)
@@ -205,7 +212,7 @@ cjt_status build_program(const std::vector<const Plan*>& plans, const std::vecto
                              bnd_f, bnd_b)) != CJT_OK)
                 return s;
         mark(Kind::Fork);
-        add_rec_inv(pr, tasks, S, 1, rec_f, rec_b);
+        add_rec_inv(pr, tasks, 1, rec_f, rec_b);
         for (auto& c : chunks)
             if ((s = add_fft(pr, c, Src::InvAsy, Sink::InvAsy, fp32, 0, fp32 ? "hahn_inv_cols_fp32" : "hahn_inv_cols",
                              fp32 ? "hahn_inv_rows_fp32" : "hahn_inv_rows", asy_f, asy_b, job_parallel)) != CJT_OK)

@@ -44,6 +44,11 @@ struct Plan {
     d4 *i0 = nullptr, *ip = nullptr, *im = nullptr;
     RecTask* d_tasks_f = nullptr;
     RecTask* d_tasks_i = nullptr;
+    bool own_arena = false;      // arena allocated by build_plan_device (else lent by the caller)
+    size_t scratch_bytes = 0;    // device scratch build_plan_device needs
+    // complex FFT geometries of the two grids, FP64 (geo_*) and in the
+    // precision of the Hahn-block FFTs (geob_*); chirp-z tables in the arena
+    FftGeom geo_f{}, geo_i{}, geob_f{}, geob_i{};
 };
 
 constexpr int kRecWidthFwd = 64 * 4;    // points per forward recurrence task (4 per lane)
@@ -52,7 +57,22 @@ constexpr int kRecWidthInv = 64 * 4;    // points per inverse task (4 per lane)
 void compute_partition(int64_t G, int64_t cap, double a, double b, int M, Part* P);
 void choose_partitions(int64_t N, double a, double b, int M, Part* f, Part* inv);
 void build_tasks(const Part& P, int width, std::vector<RecTask>* out, int64_t* part_total);
-cjt_status build_plan_device(Plan* P, hipStream_t st);
-cjt_status fft_geometry(int64_t L, bool fp32, hipStream_t st, FftGeom* g);
+// Argument checks shared by every entry point that creates plans.
+cjt_status check_args(int64_t N, double alpha, double beta, int M, unsigned flags);
+// Host half of plan creation: partitions, recurrence tasks, arena layout.
+void plan_host(Plan* P, int64_t N, double alpha, double beta, int M, unsigned flags);
+// Sizes of the device arena and of the build scratch (host only; after the
+// partitions and tasks are set).
+void plan_layout(Plan* P);
+// Computes the plan's device arrays on st into `arena` (arena_bytes) using
+// `scratch` (scratch_bytes); either may be null, then it is allocated here
+// (the arena is then owned by the plan).  Returns after the work completed.
+cjt_status build_plan_device(Plan* P, hipStream_t st, void* arena, void* scratch);
+// Shape of a length-L complex FFT without tables.
+void geometry_shape(int64_t L, FftGeom* g);
+// Shape plus tables: shared power-of-two twiddles; for lengths that are not
+// powers of two, chirp-z tables built into mem (chirp_table_bytes) with
+// scratch (chirp_scratch_bytes), asynchronously on st.
+cjt_status fft_geometry(int64_t L, bool fp32, hipStream_t st, FftGeom* g, char* mem, char* scratch);
 
 }  // namespace cjt

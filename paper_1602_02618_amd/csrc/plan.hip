@@ -369,126 +369,202 @@ static void moments_host(int64_t L, double a, double b, std::vector<double>* mu)
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-cjt_status build_plan_device(Plan* P, hipStream_t st)
+namespace {
+
+// Byte offsets of a plan's device arrays in its arena.
+struct Layout {
+    size_t C, UVf, UVi, W, S, R, Tf, Ti, Mu, Gf, Gi, Gbf, Gbi, total;
+};
+
+Layout layout_of(const Plan& P)
 {
-    const int64_t N = P->N;
-    const int M = std::max(P->fwd.M, P->inv.M);
-    const int64_t nf = N + 1, ni = 2 * N + 1;
-    // layout
+    const int64_t N = P.N, nf = N + 1, ni = 2 * N + 1;
+    const int M = std::max(P.fwd.M, P.inv.M);
+    const bool fp32 = (P.flags & CJT_FP32_BULK) != 0;
+    Layout l{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
         off += align_up(bytes);
         return o;
     };
-    const size_t oC = take(sizeof(double) * (size_t)M * nf);
-    const size_t oUVf = take(sizeof(cx<double>) * (size_t)P->fwd.M * nf);
-    const size_t oUVi = take(sizeof(cx<double>) * (size_t)P->inv.M * ni);
-    const size_t oW = take(sizeof(double) * ni);
-    const size_t oS = take(sizeof(double) * nf);
-    const size_t oR = take(sizeof(d4) * 6 * (size_t)nf);
-    const size_t oTf = take(sizeof(RecTask) * std::max<size_t>(1, P->tasks_f.size()));
-    const size_t oTi = take(sizeof(RecTask) * std::max<size_t>(1, P->tasks_i.size()));
-    const size_t oMu = take(sizeof(double) * ni);
-    P->arena_bytes = off;
-    CJT_HIP_TRY(hipMalloc(&P->arena, off));
-    char* base = (char*)P->arena;
-    P->C = (double*)(base + oC);
-    P->uv_f = (cx<double>*)(base + oUVf);
-    P->uv_i = (cx<double>*)(base + oUVi);
-    P->w = (double*)(base + oW);
-    P->s = (double*)(base + oS);
-    d4* R = (d4*)(base + oR);
+    l.C = take(sizeof(double) * (size_t)M * nf);
+    l.UVf = take(sizeof(cx<double>) * (size_t)P.fwd.M * nf);
+    l.UVi = take(sizeof(cx<double>) * (size_t)P.inv.M * ni);
+    l.W = take(sizeof(double) * ni);
+    l.S = take(sizeof(double) * nf);
+    l.R = take(sizeof(d4) * 6 * (size_t)nf);
+    l.Tf = take(sizeof(RecTask) * std::max<size_t>(1, P.tasks_f.size()));
+    l.Ti = take(sizeof(RecTask) * std::max<size_t>(1, P.tasks_i.size()));
+    l.Mu = take(sizeof(double) * ni);
+    FftGeom gf, gi;
+    geometry_shape(N, &gf);
+    geometry_shape(2 * N, &gi);
+    l.Gf = take(gf.bluestein ? chirp_table_bytes(gf, false) : 0);
+    l.Gi = take(gi.bluestein ? chirp_table_bytes(gi, false) : 0);
+    l.Gbf = take(fp32 && gf.bluestein ? chirp_table_bytes(gf, true) : 0);
+    l.Gbi = take(fp32 && gi.bluestein ? chirp_table_bytes(gi, true) : 0);
+    l.total = off;
+    return l;
+}
+
+// The Clenshaw--Curtis weights program: one DCT-I of the moments on the 2N grid.
+cjt_status weights_program(const Plan& P, const FftGeom& gi, Program* pr)
+{
+    ExecDesc d{};
+    d.N = P.N;
+    d.G = 2 * P.N;
+    d.alpha = P.alpha;
+    d.beta = P.beta;
+    d.geo = gi;
+    d.geob = gi;
+    pr->descs.push_back(d);
+    std::vector<double> fl(1, 0.0), by(1, 0.0);
+    return add_fft(*pr, std::vector<int>{0}, Src::Moments, Sink::Weights, false, 0, nullptr, nullptr, fl, by);
+}
+
+}  // namespace
+
+void plan_layout(Plan* P)
+{
+    const Layout l = layout_of(*P);
+    P->arena_bytes = l.total;
+    FftGeom gf, gi;
+    geometry_shape(P->N, &gf);
+    geometry_shape(2 * P->N, &gi);
+    const bool fp32 = (P->flags & CJT_FP32_BULK) != 0;
+    size_t scr = 0;
+    for (const FftGeom* g : {&gf, &gi})
+        if (g->bluestein) scr = std::max(scr, chirp_scratch_bytes(*g, fp32));
+    Program pr;
+    size_t items = 1;
+    if (weights_program(*P, gi, &pr) == CJT_OK) items = std::max<size_t>(1, pr.items.size());
+    const size_t wprog = align_up(sizeof(ExecDesc)) + align_up(sizeof(Item) * items) + fft_job_bytes(2 * P->N, false);
+    P->scratch_bytes = std::max(scr, wprog);
+}
+
+cjt_status build_plan_device(Plan* P, hipStream_t st, void* arena, void* scratch)
+{
+    const int64_t N = P->N;
+    const int M = std::max(P->fwd.M, P->inv.M);
+    const int64_t nf = N + 1, ni = 2 * N + 1;
+    const bool fp32 = (P->flags & CJT_FP32_BULK) != 0;
+    const Layout ly = layout_of(*P);
+    P->arena_bytes = ly.total;
+    if (!arena) {
+        CJT_HIP_TRY(hipMalloc(&arena, ly.total));
+        P->own_arena = true;
+    }
+    P->arena = arena;
+    char* scr = (char*)scratch;
+    if (!scr && hipMalloc((void**)&scr, std::max<size_t>(P->scratch_bytes, 256)) != hipSuccess)
+        return fail(CJT_ENOMEM, "plan scratch allocation failed");
+    char* base = (char*)arena;
+    P->C = (double*)(base + ly.C);
+    P->uv_f = (cx<double>*)(base + ly.UVf);
+    P->uv_i = (cx<double>*)(base + ly.UVi);
+    P->w = (double*)(base + ly.W);
+    P->s = (double*)(base + ly.S);
+    d4* R = (d4*)(base + ly.R);
     P->f0 = R;
     P->fp = R + nf;
     P->fm = R + 2 * nf;
     P->i0 = R + 3 * nf;
     P->ip = R + 4 * nf;
     P->im = R + 5 * nf;
-    P->d_tasks_f = (RecTask*)(base + oTf);
-    P->d_tasks_i = (RecTask*)(base + oTi);
-    double* mu = (double*)(base + oMu);
+    P->d_tasks_f = (RecTask*)(base + ly.Tf);
+    P->d_tasks_i = (RecTask*)(base + ly.Ti);
+    double* mu = (double*)(base + ly.Mu);
 
-    const double a = P->alpha, b = P->beta;
-    const unsigned bs = 256;
-    auto grid = [&](int64_t n) { return dim3((unsigned)((n + bs - 1) / bs)); };
-    hipLaunchKernelGGL(k_plan_rec, grid(nf), dim3(bs), 0, st, N, a, b, P->f0, P->fp, P->fm, P->i0, P->ip, P->im);
-    CJT_HIP_TRY(hipGetLastError());
-    int64_t nlo = N + 1;
-    for (int k = 0; k < P->fwd.nblk; ++k) nlo = std::min(nlo, P->fwd.deg_lo[k]);
-    for (int k = 0; k < P->inv.nblk; ++k) nlo = std::min(nlo, P->inv.deg_lo[k]);
-    hipLaunchKernelGGL(k_plan_C, grid(nf), dim3(bs), 0, st, N, a, b, M, nlo, P->C);
-    CJT_HIP_TRY(hipGetLastError());
-    const int64_t flo = P->fwd.nblk ? P->fwd.win_lo[0] : 1, fhi = P->fwd.nblk ? P->fwd.win_hi[0] : 0;
-    hipLaunchKernelGGL(k_plan_uv, grid(nf), dim3(bs), 0, st, N, a, b, P->fwd.M, flo, fhi, P->uv_f);
-    CJT_HIP_TRY(hipGetLastError());
-    const int64_t ilo = P->inv.nblk ? P->inv.win_lo[0] : 1, ihi = P->inv.nblk ? P->inv.win_hi[0] : 0;
-    hipLaunchKernelGGL(k_plan_uv, grid(ni), dim3(bs), 0, st, 2 * N, a, b, P->inv.M, ilo, ihi, P->uv_i);
-    CJT_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_plan_s, grid(nf), dim3(bs), 0, st, N, a, b, P->s);
-    CJT_HIP_TRY(hipGetLastError());
-    if (!P->tasks_f.empty())
-        CJT_HIP_TRY(hipMemcpyAsync(P->d_tasks_f, P->tasks_f.data(), sizeof(RecTask) * P->tasks_f.size(),
-                                   hipMemcpyHostToDevice, st));
-    if (!P->tasks_i.empty())
-        CJT_HIP_TRY(hipMemcpyAsync(P->d_tasks_i, P->tasks_i.data(), sizeof(RecTask) * P->tasks_i.size(),
-                                   hipMemcpyHostToDevice, st));
+    cjt_status stt = CJT_OK;
     std::vector<double> hmu;
-    moments_host(2 * N, a, b, &hmu);
-    CJT_HIP_TRY(hipMemcpyAsync(mu, hmu.data(), sizeof(double) * ni, hipMemcpyHostToDevice, st));
-    // Clenshaw--Curtis weights on the 2N grid: one DCT-I of the moments.
-    ExecDesc d{};
-    d.N = N;
-    d.G = 2 * N;
-    d.alpha = a;
-    d.beta = b;
-    d.in = mu;
-    d.out = P->w;
-    cjt_status stt = fft_geometry(2 * N, false, st, &d.geo);
-    if (stt != CJT_OK) return stt;
-    d.geob = d.geo;
-    const size_t tmp_bytes = fft_job_bytes(2 * N, false);
-    const size_t dbytes = (sizeof(ExecDesc) + 255) & ~(size_t)255;
-    char* buf = nullptr;  // [descriptor | items | FFT intermediates]
-    Program pr;
-    pr.descs.push_back(d);
-    std::vector<double> fl(1, 0.0), by(1, 0.0);
-    stt = add_fft(pr, std::vector<int>{0}, Src::Moments, Sink::Weights, false, 0, nullptr, nullptr, fl, by);
-    if (stt != CJT_OK) return stt;
-    const size_t ibytes = (sizeof(Item) * pr.items.size() + 255) & ~(size_t)255;
-    CJT_HIP_TRY(hipMalloc(&buf, dbytes + ibytes + tmp_bytes));
-    pr.descs[0].tmp = tmp_bytes ? (void*)(buf + dbytes + ibytes) : nullptr;
     do {
-        if (hipMemcpyAsync(buf, pr.descs.data(), sizeof(ExecDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(buf + dbytes, pr.items.data(), sizeof(Item) * pr.items.size(), hipMemcpyHostToDevice,
+        // FFT geometries of both grids; chirp-z tables live in the arena
+        if ((stt = fft_geometry(N, false, st, &P->geo_f, base + ly.Gf, scr)) != CJT_OK) break;
+        if ((stt = fft_geometry(2 * N, false, st, &P->geo_i, base + ly.Gi, scr)) != CJT_OK) break;
+        P->geob_f = P->geo_f;
+        P->geob_i = P->geo_i;
+        if (fp32) {
+            if ((stt = fft_geometry(N, true, st, &P->geob_f, base + ly.Gbf, scr)) != CJT_OK) break;
+            if ((stt = fft_geometry(2 * N, true, st, &P->geob_i, base + ly.Gbi, scr)) != CJT_OK) break;
+        }
+        const double a = P->alpha, b = P->beta;
+        const unsigned bs = 256;
+        auto grid = [&](int64_t n) { return dim3((unsigned)((n + bs - 1) / bs)); };
+        hipLaunchKernelGGL(k_plan_rec, grid(nf), dim3(bs), 0, st, N, a, b, P->f0, P->fp, P->fm, P->i0, P->ip,
+                           P->im);
+        int64_t nlo = N + 1;
+        for (int k = 0; k < P->fwd.nblk; ++k) nlo = std::min(nlo, P->fwd.deg_lo[k]);
+        for (int k = 0; k < P->inv.nblk; ++k) nlo = std::min(nlo, P->inv.deg_lo[k]);
+        hipLaunchKernelGGL(k_plan_C, grid(nf), dim3(bs), 0, st, N, a, b, M, nlo, P->C);
+        const int64_t flo = P->fwd.nblk ? P->fwd.win_lo[0] : 1, fhi = P->fwd.nblk ? P->fwd.win_hi[0] : 0;
+        hipLaunchKernelGGL(k_plan_uv, grid(nf), dim3(bs), 0, st, N, a, b, P->fwd.M, flo, fhi, P->uv_f);
+        const int64_t ilo = P->inv.nblk ? P->inv.win_lo[0] : 1, ihi = P->inv.nblk ? P->inv.win_hi[0] : 0;
+        hipLaunchKernelGGL(k_plan_uv, grid(ni), dim3(bs), 0, st, 2 * N, a, b, P->inv.M, ilo, ihi, P->uv_i);
+        hipLaunchKernelGGL(k_plan_s, grid(nf), dim3(bs), 0, st, N, a, b, P->s);
+        if (hipGetLastError() != hipSuccess) {
+            stt = fail(CJT_EDEVICE, "plan kernel launch failed");
+            break;
+        }
+        if ((!P->tasks_f.empty() &&
+             hipMemcpyAsync(P->d_tasks_f, P->tasks_f.data(), sizeof(RecTask) * P->tasks_f.size(),
+                            hipMemcpyHostToDevice, st) != hipSuccess) ||
+            (!P->tasks_i.empty() &&
+             hipMemcpyAsync(P->d_tasks_i, P->tasks_i.data(), sizeof(RecTask) * P->tasks_i.size(),
+                            hipMemcpyHostToDevice, st) != hipSuccess)) {
+            stt = fail(CJT_EDEVICE, "task copy failed");
+            break;
+        }
+        moments_host(2 * N, a, b, &hmu);
+        if (hipMemcpyAsync(mu, hmu.data(), sizeof(double) * ni, hipMemcpyHostToDevice, st) != hipSuccess) {
+            stt = fail(CJT_EDEVICE, "moment copy failed");
+            break;
+        }
+        // Clenshaw--Curtis weights on the 2N grid: one DCT-I of the moments
+        // (scratch: [descriptor | items | FFT intermediates]).
+        Program pr;
+        if ((stt = weights_program(*P, P->geo_i, &pr)) != CJT_OK) break;
+        const size_t dbytes = align_up(sizeof(ExecDesc));
+        const size_t ibytes = align_up(sizeof(Item) * pr.items.size());
+        pr.descs[0].in = mu;
+        pr.descs[0].out = P->w;
+        pr.descs[0].tmp = fft_job_bytes(2 * N, false) ? (void*)(scr + dbytes + ibytes) : nullptr;
+        if (dbytes + ibytes + fft_job_bytes(2 * N, false) > std::max<size_t>(P->scratch_bytes, 256)) {
+            stt = fail(CJT_EINVAL, "plan scratch too small");
+            break;
+        }
+        if (hipMemcpyAsync(scr, pr.descs.data(), sizeof(ExecDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(scr + dbytes, pr.items.data(), sizeof(Item) * pr.items.size(), hipMemcpyHostToDevice,
                            st) != hipSuccess) {
             stt = fail(CJT_EDEVICE, "descriptor copy failed");
             break;
         }
         for (const Launch& L : pr.launches) {
-            stt = launch_fft(L, (const ExecDesc*)buf, (const Item*)(buf + dbytes) + L.item_off, st);
+            stt = launch_fft(L, (const ExecDesc*)scr, (const Item*)(scr + dbytes) + L.item_off, st);
             if (stt != CJT_OK) break;
         }
-        if (hipStreamSynchronize(st) != hipSuccess && stt == CJT_OK) stt = fail(CJT_EDEVICE, "plan build failed");
     } while (0);
-    (void)hipFree(buf);
-    if (stt != CJT_OK) return stt;
-    CJT_HIP_TRY(hipStreamSynchronize(st));
-    return CJT_OK;
+    if (hipStreamSynchronize(st) != hipSuccess && stt == CJT_OK) stt = fail(CJT_EDEVICE, "plan build failed");
+    if (!scratch) (void)hipFree(scr);
+    if (stt != CJT_OK && P->own_arena) {
+        (void)hipFree(P->arena);
+        P->arena = nullptr;
+        P->own_arena = false;
+    }
+    return stt;
 }
 
-// ------------------------------------------------------------------ FFT geometry cache
+// ------------------------------------------------------------------ FFT geometry
 
 namespace {
-struct GeoEntry {
+std::mutex g_tw_mu;
+struct TwEntry {
     int dev;
-    int64_t L;
+    int64_t F;
     bool fp32;
-    FftGeom g;
+    const void* tw;
 };
-std::recursive_mutex g_geo_mu;
-std::vector<std::pair<GeoEntry, const void*>> g_tw;  // power-of-two twiddle tables
-std::vector<GeoEntry> g_geo;                          // complete geometries
+std::vector<TwEntry> g_tw;  // power-of-two twiddle tables, one per (device, length, precision)
 
 int ilog2_ceil(int64_t x)
 {
@@ -510,68 +586,61 @@ void split(FftGeom* g, int lg, int64_t F)
 }  // namespace
 
 // Twiddles e^{i pi q / F}, q < 2F, of a power-of-two length F, built once per
-// (device, F, precision) and kept for the life of the process.
+// (device, F, precision) and kept for the life of the process (at most one
+// table per power of two: 2F complex values each).
 cjt_status fft_twiddles_cached(int64_t F, bool fp32, hipStream_t st, const void** out)
 {
     int dev = 0;
     CJT_HIP_TRY(hipGetDevice(&dev));
-    std::lock_guard<std::recursive_mutex> lk(g_geo_mu);
-    for (auto& e : g_tw)
-        if (e.first.dev == dev && e.first.L == F && e.first.fp32 == fp32) {
-            *out = e.second;
+    std::lock_guard<std::mutex> lk(g_tw_mu);
+    for (const TwEntry& e : g_tw)
+        if (e.dev == dev && e.F == F && e.fp32 == fp32) {
+            *out = e.tw;
             return CJT_OK;
         }
     const void* tw = nullptr;
     cjt_status s = make_twiddles(F, fp32, &tw, st);
     if (s != CJT_OK) return s;
     CJT_HIP_TRY(hipStreamSynchronize(st));
-    g_tw.push_back({GeoEntry{dev, F, fp32, FftGeom{}}, tw});
+    g_tw.push_back(TwEntry{dev, F, fp32, tw});
     *out = tw;
     return CJT_OK;
 }
 
-// Geometry of the length-L complex FFT: power-of-two lengths run directly
-// (one or two passes), every other length through the chirp-z convolution of
+// Shape of the length-L complex FFT: power-of-two lengths run directly (one
+// or two passes), every other length through the chirp-z convolution of
 // power-of-two length P >= 2L - 1.
-cjt_status fft_geometry(int64_t L, bool fp32, hipStream_t st, FftGeom* g)
+void geometry_shape(int64_t L, FftGeom* g)
+{
+    *g = FftGeom{};
+    g->L = L;
+    g->logL = ilog2_ceil(L);
+    if ((L & (L - 1)) == 0) {
+        split(g, g->logL, L);
+    } else {
+        g->bluestein = 1;
+        g->logP = ilog2_ceil(2 * L - 1);
+        g->P = (int64_t)1 << g->logP;
+        split(g, g->logP, g->P);
+    }
+}
+
+cjt_status fft_geometry(int64_t L, bool fp32, hipStream_t st, FftGeom* g, char* mem, char* scratch)
 {
     if (L < 1) return fail(CJT_EINVAL, "FFT length must be positive");
-    int dev = 0;
-    CJT_HIP_TRY(hipGetDevice(&dev));
-    std::lock_guard<std::recursive_mutex> lk(g_geo_mu);
-    for (auto& e : g_geo)
-        if (e.dev == dev && e.L == L && e.fp32 == fp32) {
-            *g = e.g;
-            return CJT_OK;
-        }
-    FftGeom x{};
-    x.L = L;
-    x.logL = ilog2_ceil(L);
-    if ((L & (L - 1)) == 0) {
-        cjt_status s = fft_twiddles_cached(L, fp32, st, &x.tw);
-        if (s != CJT_OK) return s;
-        split(&x, x.logL, L);
-        if (!x.single) {
-            if ((s = fft_twiddles_cached(x.L1, fp32, st, &x.tw1)) != CJT_OK) return s;
-            if ((s = fft_twiddles_cached(x.L2, fp32, st, &x.tw2)) != CJT_OK) return s;
-        }
-    } else {
-        x.bluestein = 1;
-        x.logP = ilog2_ceil(2 * L - 1);
-        x.P = (int64_t)1 << x.logP;
-        cjt_status s = fft_twiddles_cached(x.P, fp32, st, &x.tw);
-        if (s != CJT_OK) return s;
-        split(&x, x.logP, x.P);
-        if (!x.single) {
-            if ((s = fft_twiddles_cached(x.L1, fp32, st, &x.tw1)) != CJT_OK) return s;
-            if ((s = fft_twiddles_cached(x.L2, fp32, st, &x.tw2)) != CJT_OK) return s;
-        }
-        s = make_chirp_tables(&x, fp32, st);
-        if (s != CJT_OK) return s;
+    geometry_shape(L, g);
+    const int64_t F = g->bluestein ? g->P : L;
+    cjt_status s = fft_twiddles_cached(F, fp32, st, &g->tw);
+    if (s != CJT_OK) return s;
+    if (!g->single) {
+        if ((s = fft_twiddles_cached(g->L1, fp32, st, &g->tw1)) != CJT_OK) return s;
+        if ((s = fft_twiddles_cached(g->L2, fp32, st, &g->tw2)) != CJT_OK) return s;
     }
-    g_geo.push_back(GeoEntry{dev, L, fp32, x});
-    *g = x;
-    return CJT_OK;
+    if (g->bluestein) {
+        if (!mem || !scratch) return fail(CJT_EINVAL, "chirp-z tables need plan memory");
+        s = make_chirp_tables(g, fp32, st, mem, scratch);
+    }
+    return s;
 }
 
 }  // namespace cjt

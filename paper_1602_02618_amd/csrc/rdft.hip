@@ -400,7 +400,9 @@ __global__ void __launch_bounds__(256) k_single(const ExecDesc* __restrict__ des
     double* acc = reinterpret_cast<double*>(smem_raw + acc_off);
     for (int i = 0; i < kSlots; ++i) acc[i * nth + tid] = 0.0;
     const int njobs = Source<S>::kMulti ? d.nblk * d.M : 1;
-    for (int job = 0; job < njobs; ++job) {
+    for (int iter = 0; iter < njobs; ++iter) {
+        // terms m outer, blocks k inner: the order of the two-pass and job-parallel sums
+        const int job = Source<S>::kMulti ? (iter % d.nblk) * d.M + iter / d.nblk : 0;
         for (int t = tid; t < L; t += nth) buf[lds_pad(t)] = to_t<T>(Source<S>::load(d, job, t));
         __syncthreads();
         lds_fft<T>(buf, g.logL, 1, tw, 2 * g.L);
@@ -728,7 +730,9 @@ __global__ void __launch_bounds__(256) k_bs_single(const ExecDesc* __restrict__ 
     for (int i = 0; i < kSlots; ++i) acc[i * nth + tid] = 0.0;
     const T invP = (T)1 / (T)P;
     const int njobs = Source<S>::kMulti ? d.nblk * d.M : 1;
-    for (int job = 0; job < njobs; ++job) {
+    for (int iter = 0; iter < njobs; ++iter) {
+        // terms m outer, blocks k inner: the order of the two-pass and job-parallel sums
+        const int job = Source<S>::kMulti ? (iter % d.nblk) * d.M + iter / d.nblk : 0;
         for (int t = tid; t < P; t += nth)
             buf[lds_pad(t)] = t < L ? cmul(to_t<T>(Source<S>::load(d, job, t)), ldg(chirp + t)) : cx<T>{(T)0, (T)0};
         __syncthreads();
@@ -1202,17 +1206,36 @@ __global__ void __launch_bounds__(256) k_bl_row(FftGeom g, const cx<double>* scr
         blockIdx.x, [&](int64_t i) { return scratch[i]; }, [&](int64_t i, cx<double> v) { bl[i] = v; });
 }
 
-// Builds chirp, utw and F(b~) for g (whose L, P, split and tw are set), in FP64
-// and, if fp32, converted.  The device memory belongs to the geometry cache.
-cjt_status make_chirp_tables(FftGeom* g, bool fp32, hipStream_t st)
+namespace {
+size_t a256b(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // namespace
+
+size_t chirp_table_bytes(const FftGeom& g, bool fp32)
+{
+    const size_t e = fp32 ? sizeof(cx<float>) : sizeof(cx<double>);
+    return a256b(e * (size_t)g.L) + a256b(e * (size_t)(g.L + 1)) + a256b(e * (size_t)g.P);
+}
+
+size_t chirp_scratch_bytes(const FftGeom& g, bool fp32)
+{
+    size_t s = g.single ? 0 : a256b(sizeof(cx<double>) * (size_t)g.P);  // two-pass intermediate
+    if (fp32) s += chirp_table_bytes(g, false);                        // FP64 tables before conversion
+    return s;
+}
+
+// Builds chirp, utw and F(b~) for g (whose L, P, split and tw are set) into
+// mem (chirp_table_bytes), always in FP64 first and converted for fp32; the
+// construction uses scratch (chirp_scratch_bytes).  Asynchronous on st: the
+// tables are ready once st reaches this point.
+cjt_status make_chirp_tables(FftGeom* g, bool fp32, hipStream_t st, char* mem, char* scratch)
 {
     const int64_t L = g->L, P = g->P;
-    cx<double>* chirp = nullptr;
-    cx<double>* utw = nullptr;
-    cx<double>* bl = nullptr;
-    CJT_HIP_TRY(hipMalloc(&chirp, sizeof(cx<double>) * L));
-    CJT_HIP_TRY(hipMalloc(&utw, sizeof(cx<double>) * (L + 1)));
-    CJT_HIP_TRY(hipMalloc(&bl, sizeof(cx<double>) * P));
+    const size_t two_pass = g->single ? 0 : a256b(sizeof(cx<double>) * (size_t)P);
+    char* t64 = fp32 ? scratch + two_pass : mem;
+    cx<double>* chirp = (cx<double>*)t64;
+    cx<double>* utw = (cx<double>*)(t64 + a256b(sizeof(cx<double>) * (size_t)L));
+    cx<double>* bl = (cx<double>*)(t64 + a256b(sizeof(cx<double>) * (size_t)L) +
+                                   a256b(sizeof(cx<double>) * (size_t)(L + 1)));
     hipLaunchKernelGGL(k_chirp_tables, dim3((unsigned)((L + 1 + 255) / 256)), dim3(256), 0, st, chirp, utw, L);
     CJT_HIP_TRY(hipGetLastError());
     FftGeom g64 = *g;
@@ -1236,45 +1259,35 @@ cjt_status make_chirp_tables(FftGeom* g, bool fp32, hipStream_t st)
         hipLaunchKernelGGL(k_bl_single, dim3(1), dim3(256), lds, st, g64, bl);
         CJT_HIP_TRY(hipGetLastError());
     } else {
-        cx<double>* scratch = nullptr;
-        CJT_HIP_TRY(hipMalloc(&scratch, sizeof(cx<double>) * P));
+        cx<double>* tmp = (cx<double>*)scratch;
         const int TC = g->L1 >= 2048 ? 1 : 2048 / g->L1, TR = g->L2 >= 2048 ? 1 : 2048 / g->L2;
         const size_t lds1 = (size_t)TC * slice_stride(g->L1) * sizeof(cx<double>);
         const size_t lds2 = (size_t)TR * slice_stride(g->L2) * sizeof(cx<double>);
         s = allow_lds(k_bl_col, lds1);
         if (s == CJT_OK) s = allow_lds(k_bl_row, lds2);
         if (s != CJT_OK) return s;
-        hipLaunchKernelGGL(k_bl_col, dim3(g->L2 / TC), dim3(128), lds1, st, g64, scratch);
+        hipLaunchKernelGGL(k_bl_col, dim3(g->L2 / TC), dim3(128), lds1, st, g64, tmp);
         CJT_HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_bl_row, dim3(g->L1 / TR), dim3(TR * (g->L2 / 16)), lds2, st, g64, scratch, bl);
+        hipLaunchKernelGGL(k_bl_row, dim3(g->L1 / TR), dim3(TR * (g->L2 / 16)), lds2, st, g64, tmp, bl);
         CJT_HIP_TRY(hipGetLastError());
-        CJT_HIP_TRY(hipStreamSynchronize(st));
-        CJT_HIP_TRY(hipFree(scratch));
     }
     if (!fp32) {
         g->chirp = chirp;
         g->utw = utw;
         g->bl = bl;
     } else {
-        cx<float>* c32 = nullptr;
-        cx<float>* u32 = nullptr;
-        cx<float>* b32 = nullptr;
-        CJT_HIP_TRY(hipMalloc(&c32, sizeof(cx<float>) * L));
-        CJT_HIP_TRY(hipMalloc(&u32, sizeof(cx<float>) * (L + 1)));
-        CJT_HIP_TRY(hipMalloc(&b32, sizeof(cx<float>) * P));
+        cx<float>* c32 = (cx<float>*)mem;
+        cx<float>* u32 = (cx<float>*)(mem + a256b(sizeof(cx<float>) * (size_t)L));
+        cx<float>* b32 = (cx<float>*)(mem + a256b(sizeof(cx<float>) * (size_t)L) +
+                                      a256b(sizeof(cx<float>) * (size_t)(L + 1)));
         hipLaunchKernelGGL(k_to_float, dim3((unsigned)((L + 255) / 256)), dim3(256), 0, st, chirp, c32, L);
         hipLaunchKernelGGL(k_to_float, dim3((unsigned)((L + 256) / 256)), dim3(256), 0, st, utw, u32, L + 1);
         hipLaunchKernelGGL(k_to_float, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, bl, b32, P);
         CJT_HIP_TRY(hipGetLastError());
-        CJT_HIP_TRY(hipStreamSynchronize(st));
-        CJT_HIP_TRY(hipFree(chirp));
-        CJT_HIP_TRY(hipFree(utw));
-        CJT_HIP_TRY(hipFree(bl));
         g->chirp = c32;
         g->utw = u32;
         g->bl = b32;
     }
-    CJT_HIP_TRY(hipStreamSynchronize(st));
     return CJT_OK;
 }
 

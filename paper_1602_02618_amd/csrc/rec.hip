@@ -209,8 +209,7 @@ __device__ __forceinline__ TaskView task_of(const ExecDesc& d, int t)
 // from the unit states without c_n (the linear part); the three final states
 // go to the segment's record.
 template <bool kSplit>
-__global__ void __launch_bounds__(64) k_rec_fwd(const ExecDesc* __restrict__ descs, const Item* __restrict__ items,
-                                                int S)
+__global__ void __launch_bounds__(64) k_rec_fwd(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
 {
     __shared__ Stage sbuf[2];
     const Item it = items[blockIdx.x];
@@ -219,6 +218,7 @@ __global__ void __launch_bounds__(64) k_rec_fwd(const ExecDesc* __restrict__ des
     const int lane = threadIdx.x;
     int lo = 0, hi = tk.cut;
     if (kSplit) {
+        const int S = d.rec_seg;
         const int sl = seg_len(tk.cut, seg_count(tk.cut, S));
         lo = it.b * sl;
         hi = min(tk.cut, lo + sl);
@@ -343,8 +343,7 @@ __global__ void __launch_bounds__(64) k_rec_fwd_combine(const ExecDesc* __restri
 // (g_j, 0) for an unsplit task or records 4, 5 of the slot, and each degree's
 // values are summed over the task's points into part[off + n].
 template <bool kMaps>
-__global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ descs, const Item* __restrict__ items,
-                                                int S)
+__global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
 {
     __shared__ double red[kChunk][64 + 1];
     __shared__ Stage sbuf[2];
@@ -356,6 +355,7 @@ __global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ des
     const bool split = it.c >= 0;
     int lo = 0, hi = tk.cut;
     if (split) {
+        const int S = d.rec_seg;
         const int sl = seg_len(tk.cut, seg_count(tk.cut, S));
         lo = it.b * sl;
         hi = min(tk.cut, lo + sl);
@@ -529,7 +529,7 @@ __global__ void __launch_bounds__(256) k_rec_inv_reduce(const ExecDesc* __restri
 
 // ------------------------------------------------------------------ host side
 
-int32_t rec_segment_length(const Program& pr, const std::vector<const RecTask*>& tasks)
+int32_t rec_segment_length(const Program& pr, const std::vector<const RecTask*>& tasks, const std::vector<int>& which)
 {
     if (const char* e = getenv("CJT_REC_SEGMENT")) {
         const int v = atoi(e);
@@ -541,18 +541,18 @@ int32_t rec_segment_length(const Program& pr, const std::vector<const RecTask*>&
     // never below 256 steps (there the extra chains and launches cost more
     // than the chain itself)
     double W = 0.0;
-    for (size_t i = 0; i < pr.descs.size(); ++i)
+    for (int i : which)
         for (int t = 0; t < pr.descs[i].ntasks; ++t) W += (double)tasks[i][t].cut;
     const double S = std::max(256.0, std::ceil(W / 1024.0));
     const int Si = (int)std::min(S, 1.0e9);
     return (Si + kBlk - 1) / kBlk * kBlk;
 }
 
-int64_t rec_seg_doubles(const ExecDesc& d, const RecTask* tasks, int32_t S)
+int64_t rec_seg_doubles(const ExecDesc& d, const RecTask* tasks)
 {
     int64_t slots = 0;
     for (int t = 0; t < d.ntasks; ++t) {
-        const int ns = seg_count(tasks[t].cut, S);
+        const int ns = seg_count(tasks[t].cut, d.rec_seg);
         if (ns > 1) slots += ns;
     }
     return slots * kRec;
@@ -560,13 +560,12 @@ int64_t rec_seg_doubles(const ExecDesc& d, const RecTask* tasks, int32_t S)
 
 namespace {
 
-Launch rec_launch(Kind k, int stream, int nth, int32_t S, const char* name, double flops, double bytes)
+Launch rec_launch(Kind k, int stream, int nth, const char* name, double flops, double bytes)
 {
     Launch L;
     L.kind = k;
     L.stream = stream;
     L.nth = nth;
-    L.seg = S;
     L.name = name;
     L.flops = flops;
     L.bytes = bytes;
@@ -575,11 +574,11 @@ Launch rec_launch(Kind k, int stream, int nth, int32_t S, const char* name, doub
 
 // Longest chains first over the whole call, so that no long chain of a late
 // instance starts after the short ones have drained (ties keep their order).
-void by_length(std::vector<Item>& items, const Program& pr, const std::vector<const RecTask*>& tasks, int32_t S)
+void by_length(std::vector<Item>& items, const Program& pr, const std::vector<const RecTask*>& tasks)
 {
     auto len = [&](const Item& it) {
         const int cut = tasks[it.desc][it.a].cut;
-        const int ns = seg_count(cut, S);
+        const int ns = seg_count(cut, pr.descs[it.desc].rec_seg);
         return ns == 1 ? cut : seg_len(cut, ns);
     };
     std::stable_sort(items.begin(), items.end(), [&](const Item& x, const Item& y) { return len(x) > len(y); });
@@ -596,14 +595,13 @@ void push(Program& pr, Launch L, const std::vector<Item>& items)
 
 }  // namespace
 
-void add_rec_fwd(Program& pr, const std::vector<const RecTask*>& tasks, int32_t S, int stream, double flops,
-                 double bytes)
+void add_rec_fwd(Program& pr, const std::vector<const RecTask*>& tasks, int stream, double flops, double bytes)
 {
     std::vector<Item> whole, segs, comb;
     for (size_t i = 0; i < pr.descs.size(); ++i) {
         int slot = 0;
         for (int t = 0; t < pr.descs[i].ntasks; ++t) {
-            const int ns = seg_count(tasks[i][t].cut, S);
+            const int ns = seg_count(tasks[i][t].cut, pr.descs[i].rec_seg);
             if (tasks[i][t].cut <= 0) continue;
             if (ns == 1) {
                 whole.push_back(Item{(int32_t)i, t, 0, -1});
@@ -614,24 +612,23 @@ void add_rec_fwd(Program& pr, const std::vector<const RecTask*>& tasks, int32_t 
             }
         }
     }
-    by_length(segs, pr, tasks, S);
-    by_length(whole, pr, tasks, S);
-    push(pr, rec_launch(Kind::RecFwdSeg, stream, 64, S, "rec_forward", flops * 0.5, bytes * 0.5), segs);
-    push(pr, rec_launch(Kind::RecFwd, stream, 64, S, "rec_forward", segs.empty() ? flops : flops * 0.5,
+    by_length(segs, pr, tasks);
+    by_length(whole, pr, tasks);
+    push(pr, rec_launch(Kind::RecFwdSeg, stream, 64, "rec_forward", flops * 0.5, bytes * 0.5), segs);
+    push(pr, rec_launch(Kind::RecFwd, stream, 64, "rec_forward", segs.empty() ? flops : flops * 0.5,
                         segs.empty() ? bytes : bytes * 0.5),
          whole);
-    push(pr, rec_launch(Kind::RecFwdCombine, stream, 64, S, "rec_forward_combine", 0.0, 0.0), comb);
+    push(pr, rec_launch(Kind::RecFwdCombine, stream, 64, "rec_forward_combine", 0.0, 0.0), comb);
 }
 
-void add_rec_inv(Program& pr, const std::vector<const RecTask*>& tasks, int32_t S, int stream, double flops,
-                 double bytes)
+void add_rec_inv(Program& pr, const std::vector<const RecTask*>& tasks, int stream, double flops, double bytes)
 {
     std::vector<Item> maps, init, all;
     for (size_t i = 0; i < pr.descs.size(); ++i) {
         int slot = 0;
         for (int t = 0; t < pr.descs[i].ntasks; ++t) {
             if (tasks[i][t].cut <= 0) continue;
-            const int ns = seg_count(tasks[i][t].cut, S);
+            const int ns = seg_count(tasks[i][t].cut, pr.descs[i].rec_seg);
             if (ns == 1) {
                 all.push_back(Item{(int32_t)i, t, 0, -1});
             } else {
@@ -644,11 +641,11 @@ void add_rec_inv(Program& pr, const std::vector<const RecTask*>& tasks, int32_t 
             }
         }
     }
-    by_length(maps, pr, tasks, S);
-    by_length(all, pr, tasks, S);
-    push(pr, rec_launch(Kind::RecInvMaps, stream, 64, S, "rec_inverse_maps", 0.0, 0.0), maps);
-    push(pr, rec_launch(Kind::RecInvInit, stream, 64, S, "rec_inverse_init", 0.0, 0.0), init);
-    push(pr, rec_launch(Kind::RecInv, stream, 64, S, "rec_inverse", flops, bytes), all);
+    by_length(maps, pr, tasks);
+    by_length(all, pr, tasks);
+    push(pr, rec_launch(Kind::RecInvMaps, stream, 64, "rec_inverse_maps", 0.0, 0.0), maps);
+    push(pr, rec_launch(Kind::RecInvInit, stream, 64, "rec_inverse_init", 0.0, 0.0), init);
+    push(pr, rec_launch(Kind::RecInv, stream, 64, "rec_inverse", flops, bytes), all);
 }
 
 void add_rec_inv_reduce(Program& pr, int stream, double bytes)
@@ -662,7 +659,7 @@ void add_rec_inv_reduce(Program& pr, int stream, double bytes)
             (many ? wide : narrow).push_back(Item{(int32_t)i, 0, (int32_t)t, 0});
     }
     const double tot = (double)(wide.size() * 32 + narrow.size() * 256);
-    Launch L = rec_launch(Kind::RecInvReduce, stream, 256, 0, "rec_inverse_reduce", 0.0, 0.0);
+    Launch L = rec_launch(Kind::RecInvReduce, stream, 256, "rec_inverse_reduce", 0.0, 0.0);
     L.acc_off = 8;  // groups
     L.bytes = tot > 0 ? bytes * (double)(wide.size() * 32) / tot : 0.0;
     push(pr, L, wide);
@@ -677,12 +674,12 @@ cjt_status launch_rec(const Launch& L, const ExecDesc* dd, const Item* it, hipSt
     ProfScope ps(L.name, L.flops, L.bytes, s);
     const dim3 grid((unsigned)L.nitems), block(L.nth);
     switch (L.kind) {
-    case Kind::RecFwd: hipLaunchKernelGGL(k_rec_fwd<false>, grid, block, 0, s, dd, it, L.seg); break;
-    case Kind::RecFwdSeg: hipLaunchKernelGGL(k_rec_fwd<true>, grid, block, 0, s, dd, it, L.seg); break;
+    case Kind::RecFwd: hipLaunchKernelGGL(k_rec_fwd<false>, grid, block, 0, s, dd, it); break;
+    case Kind::RecFwdSeg: hipLaunchKernelGGL(k_rec_fwd<true>, grid, block, 0, s, dd, it); break;
     case Kind::RecFwdCombine: hipLaunchKernelGGL(k_rec_fwd_combine, grid, block, 0, s, dd, it); break;
-    case Kind::RecInvMaps: hipLaunchKernelGGL(k_rec_inv<true>, grid, block, 0, s, dd, it, L.seg); break;
+    case Kind::RecInvMaps: hipLaunchKernelGGL(k_rec_inv<true>, grid, block, 0, s, dd, it); break;
     case Kind::RecInvInit: hipLaunchKernelGGL(k_rec_inv_init, grid, block, 0, s, dd, it); break;
-    case Kind::RecInv: hipLaunchKernelGGL(k_rec_inv<false>, grid, block, 0, s, dd, it, L.seg); break;
+    case Kind::RecInv: hipLaunchKernelGGL(k_rec_inv<false>, grid, block, 0, s, dd, it); break;
     case Kind::RecInvReduce:
         if (L.acc_off == 8) hipLaunchKernelGGL(k_rec_inv_reduce<8>, grid, block, 0, s, dd, it);
         else hipLaunchKernelGGL(k_rec_inv_reduce<1>, grid, block, 0, s, dd, it);
