@@ -41,6 +41,15 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--workload", choices=("batch", "serve"), default="batch",
+                    help="batch: 256 x N=65536 forward+inverse (default); serve: the request stream")
+    ap.add_argument("--serve-requests", type=int, default=20000, help="requests per measured rate")
+    ap.add_argument("--serve-warmup", type=int, default=1000)
+    ap.add_argument("--serve-capacity", type=int, default=3000, help="requests of the saturating burst")
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-max-batch", type=int, default=256)
+    ap.add_argument("--serve-streams", default="pool,continuous")
+    ap.add_argument("--serve-precisions", default="fp64,fp32_bulk")
     return ap.parse_args()
 
 
@@ -64,12 +73,131 @@ def time_steps(torch, step, steps, warmup):
     return wall, per
 
 
+SERVE_NMAX = 1 << 18
+
+
+def serve_main(args):
+    """Serving stream: Poisson arrivals of forward/inverse requests (50/50),
+    N log-uniform in [128, 2^18], (alpha, beta) ~ U(-1/2, 1/2)^2, through the
+    continuous-batching server.  For each key stream (a pool of 256 keys drawn
+    once, and continuous keys) and each path (FP64, FP32-bulk): the saturated
+    capacity C from a burst, then Poisson runs at 0.5 C and 0.8 C."""
+    import torch
+    from paper_1602_02618_amd import cjt, inputs
+
+    torch.cuda.set_device(0)
+    cjt.load()
+    rng = np.random.default_rng(args.seed)
+    n_in, ring = 16, 2048
+    X = torch.as_tensor(np.stack([inputs.decaying_coeffs(rng, SERVE_NMAX, 1.0) for _ in range(n_in)]),
+                        device="cuda")
+    Y = torch.empty((ring, SERVE_NMAX + 1), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    in_ptr = [X[i].data_ptr() for i in range(n_in)]
+    out_ptr = [Y[i].data_ptr() for i in range(ring)]
+    budget = int(args.serve_budget_gb * (1 << 30))
+    precs = {"fp64": 0, "fp32_bulk": cjt.CJT_FP32_BULK}
+    streams = [s for s in args.serve_streams.split(",") if s]
+    result = {}
+    base = [0]
+
+    def replay(srv, req, lo, hi, arrivals, prec):
+        fwd, Ns, al, be = req
+        idx = range(lo, hi)
+        flags = [(cjt.CJT_DIR_FWD if fwd[i] else cjt.CJT_DIR_INV) | prec for i in idx]
+        d_in = [in_ptr[i % n_in] for i in idx]
+        d_out = [out_ptr[(base[0] + j) % ring] for j in range(hi - lo)]
+        base[0] += hi - lo
+        tickets = cjt.cjt_server_replay(srv, flags, Ns[lo:hi], al[lo:hi], be[lo:hi], d_in, d_out, arrivals)
+        res = [srv.wait(t) for t in tickets]
+        bad = [st for st, _ in res if st != cjt.CJT_OK]
+        if bad:
+            raise RuntimeError(f"{len(bad)} requests failed, first status {bad[0]}")
+        done = np.asarray(arrivals) + np.array([lat for _, lat in res])
+        return float(done.max() - np.min(arrivals)) * 1e-6  # seconds from first arrival to last completion
+
+    for sname in streams:
+        pool = 256 if sname == "pool" else 0
+        total = args.serve_warmup + args.serve_capacity + 2 * args.serve_requests
+        req = inputs.serving_requests(total, args.seed + (1 if pool else 2), key_pool=pool)
+        for pname in [p for p in args.serve_precisions.split(",") if p]:
+            prec = precs[pname]
+            rec = {}
+            with cjt.cjt_server_create(budget, max_batch=args.serve_max_batch) as srv:
+                pos = 0
+                w = args.serve_warmup
+                replay(srv, req, pos, pos + w, np.zeros(w), prec)
+                pos += w
+                srv.stats(reset=True)
+                n = args.serve_capacity
+                span = replay(srv, req, pos, pos + n, np.zeros(n), prec)
+                pos += n
+                st = srv.stats(reset=True)
+                C = n / span
+                rec["capacity_req_s"] = C
+                rec["capacity_batch_mean"] = st.mean_batch
+                log(f"serve {sname}/{pname}: capacity {C:.0f} req/s (burst of {n}, mean batch {st.mean_batch:.1f}, "
+                    f"hits {st.plan_hits} misses {st.plan_misses})")
+                for frac in (0.5, 0.8):
+                    n = args.serve_requests
+                    rate = frac * C
+                    arr = inputs.poisson_arrivals(n, rate, args.seed + int(frac * 10))
+                    span = replay(srv, req, pos, pos + n, arr, prec)
+                    pos += n
+                    st = srv.stats(reset=True)
+                    hit = st.plan_hits / max(st.plan_hits + st.plan_misses, 1)
+                    rec[f"{frac}C"] = {"rate_req_s": rate, "requests": n, "throughput_req_s": n / span,
+                                       "p50_us": st.lat_p50_us, "p99_us": st.lat_p99_us, "mean_us": st.lat_mean_us,
+                                       "max_us": st.lat_max_us, "mean_batch": st.mean_batch, "plan_hit_rate": hit,
+                                       "plan_evictions": st.plan_evictions, "admission_stalls": st.admission_stalls,
+                                       "peak_used_GiB": st.peak_used_bytes / 2**30}
+                    log(f"  {frac}C = {rate:.0f} req/s: {n / span:.0f} req/s served, p50 {st.lat_p50_us:.0f} us, "
+                        f"p99 {st.lat_p99_us:.0f} us, mean batch {st.mean_batch:.1f}, hit rate {hit:.3f}, "
+                        f"evictions {st.plan_evictions}, peak {st.peak_used_bytes / 2**30:.1f} GiB")
+            result[f"{sname}/{pname}"] = rec
+    # FP32-bulk against the FP64 path on the same requests (pool keys)
+    acc = None
+    if "fp32_bulk" in args.serve_precisions and "fp64" in args.serve_precisions:
+        req = inputs.serving_requests(64, args.seed + 7, key_pool=256)
+        outs = {}
+        for pname in ("fp64", "fp32_bulk"):
+            base[0] = 0
+            with cjt.cjt_server_create(budget, max_batch=args.serve_max_batch) as srv:
+                replay(srv, req, 0, 64, np.zeros(64), precs[pname])
+            outs[pname] = [Y[i, : int(req[1][i]) + 1].cpu().numpy() for i in range(64)]
+        errs = [float(np.linalg.norm(outs["fp32_bulk"][i] - outs["fp64"][i]) / np.linalg.norm(outs["fp64"][i]))
+                for i in range(64)]
+        acc = {"requests": 64, "max_rel2": max(errs), "median_rel2": float(np.median(errs))}
+        log(f"fp32-bulk vs fp64 path on 64 requests: max rel-2 {acc['max_rel2']:.2e}")
+    head = result.get("pool/fp64", next(iter(result.values())))
+    out = {
+        "metric": "CJT serving: requests/s and p50/p99 latency (arrival to completion) at 0.5C and 0.8C",
+        "value": head["0.8C"]["throughput_req_s"],
+        "unit": "requests/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Poisson request stream, forward/inverse 50/50, N log-uniform in [128, 2^18], "
+                               "(alpha,beta)~U(-1/2,1/2)^2, c_n=randn/(n+1); key streams: pool of 256 keys, "
+                               "continuous keys", "budget_GiB": args.serve_budget_gb,
+                   "max_batch": args.serve_max_batch, "requests_per_rate": args.serve_requests,
+                   "seed": args.seed},
+        "streams": result,
+        "fp32_bulk_vs_fp64": acc,
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); independent transforms would shard "
               "across GPUs with no exchange, but no multi-GPU path is built.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serve":
+        serve_main(args)
+        return
     import torch
     from paper_1602_02618_amd import cjt, inputs
 

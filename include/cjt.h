@@ -173,8 +173,9 @@ cjt_status cjt_batch_destroy(cjt_batch_t batch);
  * its call, host clock) when the call's event completes.
  *
  * Memory: the server allocates its whole HBM budget once at creation and
- * never more.  It holds the execution workspace (workspace_bytes), the
- * descriptor buffers of the calls in flight, and resident plans keyed by
+ * never more.  It holds the execution workspace (workspace_bytes), one
+ * descriptor buffer of max(16 MiB, max_batch x 256 KiB) per call in flight
+ * (a call whose work items do not fit is split), and resident plans keyed by
  * (N, alpha, beta, precision), least recently used first out when a new plan
  * does not fit; a plan used by a queued or running call is never evicted.
  * A request whose plan or workspace cannot fit even in an empty server fails

@@ -20,6 +20,19 @@
 
 namespace cjt {
 
+// Keeps LDS reads on their side of the barrier that follows them.  Some
+// compiler passes treat s_barrier as touching no memory and may sink a load
+// whose only use lies past the barrier below it, where it races with the
+// other threads' writes of the next phase.  This empty statement has side
+// effects and consumes the loaded registers, so every load issued before it
+// completes before it, and it stays above the barrier.  Call it once after
+// all loads of a phase have been issued (they still overlap in flight).
+template <typename T>
+__device__ __forceinline__ void lds_pin(cx<T>& a)
+{
+    asm volatile("" : "+v"(a.re), "+v"(a.im));
+}
+
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
 
 // Distance between the LDS slices of consecutive transforms of length F: the
@@ -151,6 +164,10 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int F, int Ns, int lt, int
 #pragma unroll
             for (int r = 0; r < R; ++r) v[q][r] = buf[lds_pad(base + j + r * FR)];
         }
+#pragma unroll
+        for (int q = 0; q < BPT; ++q)
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds_pin(v[q][r]);
     }
     __syncthreads();
     if (active) {
@@ -252,6 +269,8 @@ __device__ __forceinline__ void fft_reg_last(cx<T> (&v)[16], const cx<T>* buf, i
         cx<T> w[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) w[r] = buf[lds_pad(j + r * FR)];
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds_pin(w[r]);
 #pragma unroll
         for (int r = 1; r < R; ++r) w[r] = cmul(w[r], ldg(tw + (r * k) * twmul));
         dft<T, R>(w);

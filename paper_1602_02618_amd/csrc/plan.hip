@@ -274,7 +274,15 @@ __global__ void k_plan_rec(int64_t N, double a, double b, d4* f0, d4* fp, d4* fm
 
 // C_{n,m}, m < M, for n >= nlo (zero below): eq. Cnmabasy at m = 0, then the
 // m-step of eq. Cnmabrec.
-__global__ void k_plan_C(int64_t N, double a, double b, int M, int64_t nlo, double* C)
+// Power-of-two exponents e_m of the Hahn terms: C_{n,m} is stored times 2^e_m
+// and (u_m, v_m) times 2^-e_m, so every product C_{n,m} (u_m, v_m) is
+// unchanged exactly while the inputs of FP32 block transforms (C_{n,m} c_n,
+// or (u_m, v_m) g) stay inside the FP32 exponent range.  Zero for FP64 plans.
+struct TermScale {
+    int e[kMaxM];
+};
+
+__global__ void k_plan_C(int64_t N, double a, double b, int M, int64_t nlo, TermScale ts, double* C)
 {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n > N) return;
@@ -284,10 +292,10 @@ __global__ void k_plan_C(int64_t N, double a, double b, int M, int64_t nlo, doub
     }
     const double dn = (double)n;
     double c = hahn_C(dn, 0, a, b);
-    C[n] = c;
+    C[n] = ldexp(c, ts.e[0]);
     for (int m = 1; m < M; ++m) {
         c /= 2.0 * (2.0 * dn + a + b + m + 1.0);
-        C[(int64_t)m * (N + 1) + n] = c;
+        C[(int64_t)m * (N + 1) + n] = ldexp(c, ts.e[m]);
     }
 }
 
@@ -296,7 +304,8 @@ __global__ void k_plan_C(int64_t N, double a, double b, int M, int64_t nlo, doub
 // with theta_{m,l} = (a + l + 1/2) pi/2 - (a + b + m + 1) theta/2 (Sec. 2.1, eq. Jacasyuv):
 // = K c^-m e^{i phi_0} e^{-i m theta/2} sum_l a_l b_{m-l} (i t)^l,
 //   t = cot(theta/2), K = s^-(a+1/2) c^-(b+1/2), phi_0 = (a+1/2) pi/2 - (a+b+1) theta/2.
-__global__ void k_plan_uv(int64_t G, double a, double b, int M, int64_t lo, int64_t hi, cx<double>* uv)
+__global__ void k_plan_uv(int64_t G, double a, double b, int M, int64_t lo, int64_t hi, TermScale ts,
+                          cx<double>* uv)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i > G) return;
@@ -338,7 +347,7 @@ __global__ void k_plan_uv(int64_t G, double a, double b, int M, int64_t lo, int6
         const double ei = e0s * rc - e0c * rs;
         const double vr = cm * (er * wr - ei * wi);
         const double vi = cm * (er * wi + ei * wr);
-        uv[(int64_t)m * (G + 1) + i] = {vr, vi};
+        uv[(int64_t)m * (G + 1) + i] = {ldexp(vr, -ts.e[m]), ldexp(vi, -ts.e[m])};
         cm *= ic;
     }
 }
@@ -370,6 +379,47 @@ static void moments_host(int64_t L, double a, double b, std::vector<double>* mu)
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 namespace {
+
+// log2 of a bound of |u_m + i v_m| at theta (the sum of the absolute values of
+// the terms of eq. Jacasyuv).
+double log2_uv_bound(double theta, int m, double a, double b, const double* ca, const double* cb)
+{
+    const double s = sin(0.5 * theta), c = cos(0.5 * theta), t = c / s;
+    double sum = 0.0, tp = 1.0;
+    for (int l = 0; l <= m; ++l) {
+        sum += fabs(ca[l] * cb[m - l]) * tp;
+        tp *= t;
+    }
+    return (-(a + 0.5) * log(s) - (b + 0.5 + m) * log(c) + log(sum)) / log(2.0);
+}
+
+// Term exponents of an FP32-bulk plan: e_m scales the largest (u_m, v_m) on
+// the block-0 windows of both grids (the widest windows) to about 1; then
+// C_{n,m} 2^e_m is at most about the Hahn term bound on those windows, which
+// is below 1 there.  FP64 plans keep e_m = 0.
+TermScale term_scale(const Plan& P)
+{
+    TermScale ts{};
+    if (!(P.flags & CJT_FP32_BULK)) return ts;
+    const int M = std::max(P.fwd.M, P.inv.M);
+    double ca[kMaxM + 1], cb[kMaxM + 1];
+    hahn_pochhammer(M, P.alpha, P.beta, ca, cb);
+    for (int m = 0; m < M; ++m) {
+        double e = 0.0;
+        bool any = false;
+        for (const Part* pt : {&P.fwd, &P.inv}) {
+            if (pt->nblk == 0) continue;
+            for (int64_t i : {pt->win_lo[0], pt->win_hi[0]}) {
+                if (i <= 0 || i >= pt->G) continue;
+                const double l2 = log2_uv_bound(kPi * (double)i / (double)pt->G, m, P.alpha, P.beta, ca, cb);
+                e = any ? std::max(e, l2) : l2;
+                any = true;
+            }
+        }
+        ts.e[m] = any ? (int)std::min(std::max(floor(e), -900.0), 900.0) : 0;
+    }
+    return ts;
+}
 
 // Byte offsets of a plan's device arrays in its arena.
 struct Layout {
@@ -496,11 +546,12 @@ cjt_status build_plan_device(Plan* P, hipStream_t st, void* arena, void* scratch
         int64_t nlo = N + 1;
         for (int k = 0; k < P->fwd.nblk; ++k) nlo = std::min(nlo, P->fwd.deg_lo[k]);
         for (int k = 0; k < P->inv.nblk; ++k) nlo = std::min(nlo, P->inv.deg_lo[k]);
-        hipLaunchKernelGGL(k_plan_C, grid(nf), dim3(bs), 0, st, N, a, b, M, nlo, P->C);
+        const TermScale ts = term_scale(*P);
+        hipLaunchKernelGGL(k_plan_C, grid(nf), dim3(bs), 0, st, N, a, b, M, nlo, ts, P->C);
         const int64_t flo = P->fwd.nblk ? P->fwd.win_lo[0] : 1, fhi = P->fwd.nblk ? P->fwd.win_hi[0] : 0;
-        hipLaunchKernelGGL(k_plan_uv, grid(nf), dim3(bs), 0, st, N, a, b, P->fwd.M, flo, fhi, P->uv_f);
+        hipLaunchKernelGGL(k_plan_uv, grid(nf), dim3(bs), 0, st, N, a, b, P->fwd.M, flo, fhi, ts, P->uv_f);
         const int64_t ilo = P->inv.nblk ? P->inv.win_lo[0] : 1, ihi = P->inv.nblk ? P->inv.win_hi[0] : 0;
-        hipLaunchKernelGGL(k_plan_uv, grid(ni), dim3(bs), 0, st, 2 * N, a, b, P->inv.M, ilo, ihi, P->uv_i);
+        hipLaunchKernelGGL(k_plan_uv, grid(ni), dim3(bs), 0, st, 2 * N, a, b, P->inv.M, ilo, ihi, ts, P->uv_i);
         hipLaunchKernelGGL(k_plan_s, grid(nf), dim3(bs), 0, st, N, a, b, P->s);
         if (hipGetLastError() != hipSuccess) {
             stt = fail(CJT_EDEVICE, "plan kernel launch failed");

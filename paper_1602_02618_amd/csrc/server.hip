@@ -130,6 +130,7 @@ struct Request {
     double* out;
     Clock::time_point arrival;
     Entry* plan;
+    bool made_plan;  // its plan was made for it (a cache miss)
 };
 
 struct Result {
@@ -229,18 +230,17 @@ bool alloc_evicting(cjt_server_s* S, size_t bytes, size_t* off)
     return true;
 }
 
-// Resident plan for r, made if absent.  CJT_EBUSY: it does not fit now
-// because every other plan in the heap is in use.
-cjt_status get_plan(cjt_server_s* S, const Request& r, Entry** out)
+// Resident plan for r, made if absent (*made set).  CJT_EBUSY: it does not
+// fit now because every other plan in the heap is in use.
+cjt_status get_plan(cjt_server_s* S, const Request& r, Entry** out, bool* made)
 {
+    *made = false;
     const unsigned prec = r.flags & CJT_FP32_BULK;
     const Key k{r.N, bits_of(r.alpha), bits_of(r.beta), prec};
     auto it = S->plans.find(k);
     if (it != S->plans.end()) {
         Entry* e = it->second.get();
         S->lru.splice(S->lru.begin(), S->lru, e->lru);
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->hits += 1;
         *out = e;
         return CJT_OK;
     }
@@ -268,11 +268,11 @@ cjt_status get_plan(cjt_server_s* S, const Request& r, Entry** out)
     S->plans.emplace(k, std::move(E));
     {
         std::lock_guard<std::mutex> lk(S->mu);
-        S->misses += 1;
         S->resident += 1;
         S->plan_bytes += a256(e->P.arena_bytes);
     }
     *out = e;
+    *made = true;
     return CJT_OK;
 }
 
@@ -307,9 +307,11 @@ void form_call(cjt_server_s* S, std::vector<Request>& cand, bool others_in_fligh
 {
     std::vector<Request> take;
     for (size_t k = 0; k < cand.size(); ++k) {
-        Request r = cand[k];
+        Request& r = cand[k];
         Entry* e = nullptr;
-        cjt_status s = get_plan(S, r, &e);
+        bool made = false;
+        cjt_status s = get_plan(S, r, &e, &made);
+        if (made) r.made_plan = true;
         if (s == CJT_EBUSY) {
             if (others_in_flight || !take.empty()) {
                 back->assign(cand.begin() + (ptrdiff_t)k, cand.end());
@@ -338,8 +340,12 @@ void form_call(cjt_server_s* S, std::vector<Request>& cand, bool others_in_fligh
             call->reqs = std::move(take);
             return;
         }
-        if (s == CJT_OK && take.size() > 1) {  // too large for the workspace: run the first half now
-            const size_t h = take.size() / 2;
+        if (s == CJT_OK && take.size() > 1) {
+            // too large for the workspace or descriptor buffer: run a leading
+            // part that fits by the measured ratio, the rest goes back
+            const double over = std::max((double)b.ws_bytes / (double)S->ws_bytes, (double)meta / (double)S->meta_cap);
+            size_t h = (size_t)(0.9 * (double)take.size() / over);
+            h = std::min(std::max<size_t>(h, 1), take.size() - 1);
             std::vector<Request> rest(take.begin() + (ptrdiff_t)h, take.end());
             for (Request& r : rest) r.plan->refs.fetch_sub(1);
             back->insert(back->begin(), rest.begin(), rest.end());
@@ -407,6 +413,7 @@ void batcher_main(cjt_server_s* S)
         if (!call.reqs.empty()) {
             S->batches += 1;
             S->batched_reqs += (int64_t)call.reqs.size();
+            for (const Request& r : call.reqs) (r.made_plan ? S->misses : S->hits) += 1;
             S->calls.push_back(std::move(call));
         } else {
             S->free_slots.push_back(call.slot);
@@ -459,7 +466,7 @@ cjt_status submit_at(cjt_server_s* S, unsigned flags, int64_t N, double alpha, d
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->stop) return fail(CJT_EBUSY, "server is shutting down");
     const int64_t t = S->next_ticket++;
-    S->queue.push_back(Request{t, flags, N, alpha, beta, d_in, d_out, arrival, nullptr});
+    S->queue.push_back(Request{t, flags, N, alpha, beta, d_in, d_out, arrival, nullptr, false});
     S->results.emplace(t, Result{});
     S->pending += 1;
     S->submitted += 1;
@@ -504,7 +511,7 @@ cjt_status cjt_server_create(cjt_server_t* out, const cjt_server_config* cfg)
     if (c.M != 0 && (c.M < 2 || c.M > kMaxM)) return fail(CJT_EDOMAIN, "M must be 0 (auto) or in [2, 30]");
     if (c.workspace_bytes == 0) c.workspace_bytes = c.hbm_budget / 4;
     const size_t ws = a256(c.workspace_bytes);
-    const size_t meta_cap = a256(std::max<size_t>((size_t)4 << 20, (size_t)c.max_batch * (32u << 10)));
+    const size_t meta_cap = a256(std::max<size_t>((size_t)16 << 20, (size_t)c.max_batch * (256u << 10)));
     const size_t fixed = ws + meta_cap * (size_t)c.max_inflight;
     if (c.hbm_budget < fixed + ((size_t)1 << 20))
         return fail(CJT_EINVAL, "budget too small for the workspace and descriptor buffers");

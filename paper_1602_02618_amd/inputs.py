@@ -83,3 +83,34 @@ def batch_65536(seed=0, count=256):
 def batch_uneven(seed=0, count=4096):
     """4096 transforms, N log-uniform in [64, 16384], (alpha, beta) ~ U(-1/2, 1/2)^2."""
     return batch_log_uniform_N(count, 64, 16384, seed, r=1.0)
+
+
+def serving_requests(count, seed, nlo=128, nhi=1 << 18, key_pool=0, lo=-0.5, hi=0.5):
+    """Serving stream: per request the direction (forward with probability 1/2),
+    N log-uniform in [nlo, nhi] and (alpha, beta) ~ U(lo, hi)^2.  With
+    key_pool > 0 the (N, alpha, beta) keys are drawn once into a pool of that
+    size and each request picks one uniformly.  Returns numpy arrays
+    (forward: bool, N: int64, alpha, beta)."""
+    rng = np.random.default_rng(seed)
+    if key_pool > 0:
+        keys = [(log_uniform_int(rng, nlo, nhi), float(rng.uniform(lo, hi)), float(rng.uniform(lo, hi)))
+                for _ in range(key_pool)]
+    fwd = np.empty(count, dtype=bool)
+    N = np.empty(count, dtype=np.int64)
+    a = np.empty(count)
+    b = np.empty(count)
+    for i in range(count):
+        fwd[i] = rng.random() < 0.5
+        if key_pool > 0:
+            N[i], a[i], b[i] = keys[int(rng.integers(0, key_pool))]
+        else:
+            N[i] = log_uniform_int(rng, nlo, nhi)
+            a[i] = rng.uniform(lo, hi)
+            b[i] = rng.uniform(lo, hi)
+    return fwd, N, a, b
+
+
+def poisson_arrivals(count, rate_per_s, seed):
+    """Arrival times in microseconds of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1e6 / float(rate_per_s), count))

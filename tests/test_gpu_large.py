@@ -87,3 +87,27 @@ def test_large_inverse_round_trip(setup):
     t = tol_inv(N, inst.alpha, inst.beta)
     print(f"N={N}: |inv(fwd c) - c| / |c| = {e_rt:.2e}, bound {t:.2e} (flat bound {tol(N):.1e})")
     assert e_rt <= t
+
+
+@pytest.mark.parametrize("N", [70000, 300000])
+def test_large_any_length(setup, oracle_mod, N):
+    """Chirp-z lengths whose power-of-two convolutions run in two passes with
+    512 or more points per column (P = 2^18 .. 2^21): forward on sampled rows
+    against the oracle, inverse by the round trip."""
+    import torch
+    cjt = setup[0]
+    rng = np.random.default_rng(N)
+    a, b = float(rng.uniform(-0.5, 0.5)), float(rng.uniform(-0.5, 0.5))
+    c = inputs.decaying_coeffs(rng, N, 1.0)
+    plan = cjt.cjt_plan(N, a, b)
+    x = torch.as_tensor(c, device="cuda")
+    f = cjt.forward(plan, x)
+    g = cjt.inverse(plan, f)
+    rows = sorted(set([0, 1, 2, N // 3, N // 2, N - 1, N] + list(rng.integers(0, N + 1, 16))))
+    p_gpu = cheb_rows(f.cpu().numpy(), N, rows)
+    p_ref = oracle_mod.point_values_rows(c, a, b, np.array(rows, dtype=np.int64))
+    e = rel2(p_gpu, p_ref)
+    e_rt = rel2(g.cpu().numpy(), c)
+    print(f"N={N} M={plan.info.M}: rows rel2 {e:.2e}, round trip {e_rt:.2e}")
+    assert e <= tol(N)
+    assert e_rt <= tol_inv(N, a, b)

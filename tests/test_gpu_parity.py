@@ -223,3 +223,25 @@ def test_errors_returned(lib):
     with pytest.raises(lib.CJTError) as e:
         lib.cjt_forward(plan, x, x)
     assert e.value.status == lib.CJT_EINVAL
+
+
+@pytest.mark.parametrize("N", [3001, 12345, 65536, 100000])
+def test_fp32_bulk_two_pass_sizes(lib, N):
+    """FP32-bulk Hahn blocks at two-pass and chirp-z lengths, against the FP64
+    path of the library (itself pinned to the oracle): finite everywhere and at
+    single-precision level (the FP32 inputs of the high Hahn terms span far more
+    than the FP32 exponent range unless scaled)."""
+    import torch
+    rng = np.random.default_rng(40 + N % 97)
+    a, b = float(rng.uniform(-0.5, 0.5)), float(rng.uniform(-0.5, 0.5))
+    c = inputs.decaying_coeffs(rng, N, 1.0)
+    x = torch.as_tensor(c, device="cuda")
+    p64 = lib.cjt_plan(N, a, b, 0, lib.CJT_FP64)
+    p32 = lib.cjt_plan(N, a, b, 0, lib.CJT_FP32_BULK)
+    for fn in (lib.forward, lib.inverse):
+        y64 = fn(p64, x).cpu().numpy()
+        y32 = fn(p32, x).cpu().numpy()
+        assert np.isfinite(y32).all()
+        e = rel2(y32, y64)
+        print(f"N={N} {fn.__name__} fp32-bulk vs fp64 {e:.2e}")
+        assert e < 1e-4

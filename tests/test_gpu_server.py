@@ -105,7 +105,7 @@ def test_server_evicts_within_budget(lib):
     N = 4096
     arena = lib.cjt_plan_describe(N, 0.1, -0.2).device_bytes
     ws = 64 << 20
-    fixed = ws + 2 * (4 << 20)  # workspace + two descriptor buffers of 4 MiB (max_batch 4)
+    fixed = ws + 2 * (16 << 20)  # workspace + two descriptor buffers of 16 MiB (max_batch 4)
     budget = fixed + 3 * arena + (2 << 20)
     reqs = make_requests(lib, [N] * 10, 32, repeat_first=False)
     y, r, s = serve(lib, reqs, False, hbm_budget=budget, workspace_bytes=ws, max_batch=4)
@@ -125,7 +125,7 @@ def test_server_rejects_plan_over_budget(lib):
     fit are served by the same server."""
     import torch
     ws = 64 << 20
-    budget = ws + 2 * (4 << 20) + (3 << 20)
+    budget = ws + 2 * (16 << 20) + (3 << 20)
     big = torch.zeros(65537, dtype=torch.float64, device="cuda")
     small = torch.as_tensor(inputs.decaying_coeffs(np.random.default_rng(1), 64, 1.0), device="cuda")
     yb, ys = torch.empty_like(big), torch.empty_like(small)
