@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the latency (N=1024), N=2^20 and uneven-batch (4096 instances) measurements")
+    ap.add_argument("--pmc-calibration", action="store_true",
+                    help="after timing, copy 256 MiB on the device (the counter calibration of the traffic summary)")
     ap.add_argument("--workload", choices=("batch", "serve"), default="batch",
                     help="batch: 256 x N=65536 forward+inverse (default); serve: the request stream")
     ap.add_argument("--serve-requests", type=int, default=20000, help="requests per measured rate")
@@ -189,6 +193,84 @@ def serve_main(args):
     print(json.dumps(out))
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hahn_inv_cols_batch256_N65536_traffic.md")
+
+
+def event_ms(torch, fn, reps, warm):
+    """Median and p99 of reps calls of fn, each bracketed by events on the current stream."""
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in evs])
+    return float(np.median(t)), float(np.percentile(t, 99))
+
+
+def extra_workloads(torch, cjt, inputs, seed):
+    """The single-transform latency (N = 1024), the large transform (N = 2^20) and
+    the uneven batch of 4096 forward transforms replayed from a HIP graph."""
+    out = {}
+    inst = inputs.small_single(seed)
+    p = cjt.cjt_plan(inst.N, inst.alpha, inst.beta)
+    x = torch.as_tensor(inst.coeffs, device="cuda")
+    f = torch.empty_like(x)
+    g = torch.empty_like(x)
+    fm, f99 = event_ms(torch, lambda: cjt.cjt_forward(p, x, f), 1000, 100)
+    im, i99 = event_ms(torch, lambda: cjt.cjt_inverse(p, f, g), 1000, 100)
+    out["latency_N1024"] = {"forward_p50_us": fm * 1e3, "forward_p99_us": f99 * 1e3,
+                            "inverse_p50_us": im * 1e3, "inverse_p99_us": i99 * 1e3, "calls": 1000,
+                            "round_trip_rel_error": float(np.linalg.norm(g.cpu().numpy() - inst.coeffs)
+                                                          / np.linalg.norm(inst.coeffs))}
+    log(f"N=1024 latency: forward p50 {fm * 1e3:.1f} us p99 {f99 * 1e3:.1f} us, inverse p50 {im * 1e3:.1f} us "
+        f"p99 {i99 * 1e3:.1f} us")
+    big = inputs.large_single(seed)
+    pb = cjt.cjt_plan(big.N, big.alpha, big.beta)
+    xb = torch.as_tensor(big.coeffs, device="cuda")
+    fb = torch.empty_like(xb)
+    gb = torch.empty_like(xb)
+    fm, _ = event_ms(torch, lambda: cjt.cjt_forward(pb, xb, fb), 10, 2)
+    im, _ = event_ms(torch, lambda: cjt.cjt_inverse(pb, fb, gb), 10, 2)
+    info = pb.info
+    out["large_N2^20"] = {"forward_ms": fm, "inverse_ms": im, "M": info.M, "blocks_fwd": info.fwd.nblocks,
+                          "blocks_inv": info.inv.nblocks,
+                          "round_trip_rel_error": float(np.linalg.norm(gb.cpu().numpy() - big.coeffs)
+                                                        / np.linalg.norm(big.coeffs))}
+    log(f"N=2^20: forward {fm:.2f} ms, inverse {im:.2f} ms (M={info.M})")
+    insts = inputs.batch_log_uniform_N(4096, 64, 16384, seed, r=1.0)
+    t0 = time.perf_counter()
+    plans = [cjt.cjt_plan(i.N, i.alpha, i.beta) for i in insts]
+    t_plan = time.perf_counter() - t0
+    offs = np.concatenate([[0], np.cumsum([i.N + 1 for i in insts])]).astype(np.int64)
+    xu = torch.as_tensor(np.concatenate([i.coeffs for i in insts]), device="cuda")
+    yu = torch.empty_like(xu)
+    batch = cjt.cjt_batch_create(plans, offs, cjt.CJT_DIR_FWD)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        cjt.cjt_batch_execute(batch, xu, yu)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        cjt.cjt_batch_execute(batch, xu, yu)
+    gm, g99 = event_ms(torch, graph.replay, 100, 3)
+    om, _ = event_ms(torch, lambda: cjt.cjt_forward_batched(plans, offs, xu, yu), 10, 2)
+    coeffs = int(offs[-1])
+    out["uneven_batch_4096"] = {"graph_replay_p50_ms": gm, "graph_replay_p99_ms": g99, "one_shot_ms": om,
+                                "coefficients": coeffs, "coefficients_per_s": coeffs / (gm * 1e-3),
+                                "plan_s": t_plan, "launches": batch.info.launches,
+                                "workspace_GiB": batch.info.workspace_bytes / 2**30}
+    log(f"uneven batch of 4096: graph replay p50 {gm:.2f} ms ({coeffs / (gm * 1e-3):.3e} coeff/s), one-shot "
+        f"{om:.2f} ms, plans {t_plan:.1f} s")
+    batch.destroy()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -279,13 +361,32 @@ def main():
         err["tolerance_fp64"] = 1e-13 * math.log2(N)
         log(f"errors vs oracle (instance 0): {err}; oracle {t_cpu:.1f}s on {threads} threads")
 
+    extra = None if args.no_extra else extra_workloads(torch, cjt, inputs, args.seed)
+    if args.pmc_calibration:
+        a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     r64 = results["fp64"]
     t_step = r64["wall"] / args.steps
     kern = r64["kern"]
     top = max(kern.items(), key=lambda kv: kv[1]["total_ms"])
     tname, tv = top
-    achieved = tv["flops"] / (tv["total_ms"] * 1e-3) / 1e12
+    launches = max(tv["launches"], 1)
+    t_launch = tv["total_ms"] * 1e-3 / launches                # average launch duration (s)
+    alg_flops, alg_bytes = tv["flops"] / launches, tv["bytes"] / launches
     peak = PEAK_FP32_TFLOPS if tname.endswith("fp32") else PEAK_FP64_TFLOPS
+    # the kernel's roofline: the larger of its compute and HBM time at peak
+    alu_bound = alg_flops / (peak * 1e12) >= alg_bytes / (PEAK_HBM_GBS * 1e9)
+    if alu_bound:
+        achieved, unit, ceiling = alg_flops / t_launch / 1e12, "TFLOP/s", peak
+    else:
+        achieved, unit, ceiling = alg_bytes / t_launch / 1e9, "GB/s", PEAK_HBM_GBS
+    from paper_1602_02618_amd import profiling
+    rec = profiling.read_traffic(TRAFFIC_SUMMARY) if tname == "hahn_inv_cols" else None
+    traffic = rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"] if rec else None
     out = {
         "metric": "CJT coefficients/sec (fwd+inv) batched N=2^16; p99 latency; rel. error",
         "value": coeffs_per_step / t_step,
@@ -307,11 +408,15 @@ def main():
         "rel_error": err,
         "plan_s": {"fp64": t_plan64, "fp32_bulk": t_plan32},
         "kernels_ms_per_step": {k: v["total_ms"] / args.steps for k, v in kern.items()},
-        "roofline": {"bound": "alu", "kernel": tname, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "alg_bytes_per_launch": tv["bytes"] / max(tv["launches"], 1),
-                     "alg_flops_per_launch": tv["flops"] / max(tv["launches"], 1)},
+        "roofline": {"bound": "alu" if alu_bound else "hbm", "kernel": tname, "achieved": achieved,
+                     "peak": ceiling, "unit": unit, "frac": achieved / ceiling, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "launches_per_step": launches / args.steps, "launch_ms": t_launch * 1e3,
+                     "alg_bytes_per_launch": alg_bytes, "alg_flops_per_launch": alg_flops,
+                     "hbm_GBps_alg": alg_bytes / t_launch / 1e9,
+                     "hbm_GBps_measured": traffic / t_launch / 1e9 if traffic else None},
         "cpu_baseline": cpu,
+        "workloads": extra,
     }
     if "fp32_bulk" in results:
         r32 = results["fp32_bulk"]

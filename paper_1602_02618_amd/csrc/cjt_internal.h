@@ -55,7 +55,8 @@ struct FftGeom {
     int32_t logP;
     int64_t P;
     const void* chirp;  // [L]   e^{i pi t^2 / L}
-    const void* bl;     // [P]   FFT_P of the kernel conj(chirp) wrapped cyclically
+    const void* bl;     // [P]   FFT_P of the kernel conj(chirp) wrapped cyclically: natural order
+                        //       (one workgroup), row-major [k1][k2] for frequency k1 + L1 k2 (two passes)
     const void* utw;    // [L+1] e^{i pi s / L}, twiddles of the real-input untangling
 };
 
@@ -222,8 +223,9 @@ enum class Kind : int32_t {
     FftPass1Inv,     // inverse Hahn blocks: column pass of every block of one (term, column tile)
     FftPass2,        // row pass + untangling + sink, all jobs of an instance, one row tile
     BsSingle,        // chirp-z transform in one workgroup
-    BsCol1, BsRow1,  // chirp-z, first transform (two passes)
-    BsCol2, BsRow2,  // chirp-z, second transform (two passes)
+    BsCol1,     // chirp-z, two passes: column pass of the first transform
+    BsRowConv,  // row FFT, kernel product, inverse row FFT, in place
+    BsCol2Inv,  // inverse column FFT, chirp, to Z
     BsUntangle,      // chirp-z untangling + sink
     FftJobs,         // one job of a power-of-two single-workgroup transform, sink parts per job
     BsJobs,          // one job of a chirp-z single-workgroup transform, sink parts per job

@@ -37,6 +37,7 @@
 #include <mutex>
 #include <set>
 #include <string>
+#include <type_traits>
 
 #include "cjt_internal.h"
 #include "fft_lds.h"
@@ -630,56 +631,111 @@ __global__ void __launch_bounds__(128) k_bs_col1(const ExecDesc* __restrict__ de
         [&](int i, cx<T> v) { stg(base + i, v); });
 }
 
-// first transform, row pass: A in natural order to [P, 2P)
+// Twiddle e^{2 pi i n k / F} of slot s after fft_reg (output n = lt + u sigma(s))
+// from the two-read power split of ColTw.
+template <int LR, typename T>
+__device__ __forceinline__ cx<T> slot_twiddle(const ColTw<T>& ct, int s)
+{
+    constexpr int R = 1 << LR;
+    const int sigma = (s >> LR) + ((s & (R - 1)) << (4 - LR));
+    return cmul(ct.A[sigma >> 2], ct.p[sigma & 3]);
+}
+
+// Row pass of the convolution, in place on rows k1 (TR rows per workgroup):
+// the L2-point FFT of row k1 gives A at frequencies k1 + L1 k2; times the kernel
+// spectrum (stored row-major, [k1][k2]); the inverse L2-point FFT along the same
+// row (conjugate, forward FFT, conjugate) and the inverse column twiddle
+// e^{-2 pi i n2 k1 / P} leave B'[k1][n2], whose inverse column FFTs give the
+// convolution in natural order.  Replaces a row pass, a column pass and a row
+// pass of the plain two-transform form.
 template <typename T>
-__global__ void __launch_bounds__(256) k_bs_row1(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
+__global__ void __launch_bounds__(256) k_bs_rowconv(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
 {
     extern __shared__ unsigned char smem_raw[];
     const Item it = items[blockIdx.x];
     const ExecDesc& d = descs[it.desc];
     const FftGeom& g = geom_of<T>(d);
     cx<T>* base = bs_job<T>(d, g, it.a);
-    const int P = (int)g.P;
-    row_pass<T>(
-        reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw2), it.b,
-        [&](int i) { return ldg(base + i); }, [&](int i, cx<T> v) { stg(base + P + i, v); });
+    const int lg2 = g.logL2;
+    const int F2 = 1 << lg2;
+    const int ltr = lg2 >= 11 ? 0 : 11 - lg2;  // TR = 2048 / F2 rows
+    const int ltp = lg2 - 4;                    // threads per row: F2 / 16
+    const int tid = threadIdx.x;
+    const int rr = tid >> ltp, lt = tid & ((1 << ltp) - 1);
+    const int k1 = (it.b << ltr) + rr;
+    cx<T>* slice = reinterpret_cast<cx<T>*>(smem_raw) + rr * slice_stride(F2);
+    const cx<T>* tw2 = reinterpret_cast<const cx<T>*>(g.tw2);
+    const cx<T>* blT = reinterpret_cast<const cx<T>*>(g.bl) + ((int64_t)k1 << lg2);
+    cx<T>* row = base + ((int64_t)k1 << lg2);
+    cx<T> v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = ldg(row + lt + (r << ltp));
+    fft_reg<T>(v, slice, lg2, lt, true, tw2, 2 * F2);
+    // v[s] = A_{k1 + L1 k2}, k2 = fft_out_index(s): product with the kernel
+    // spectrum, conjugated, redistributed for the second row FFT
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int k2 = fft_out_index(s, lt, lg2);
+        slice[lds_pad(k2)] = conj(cmul(v[s], ldg(blT + k2)));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = slice[lds_pad(lt + (r << ltp))];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) lds_pin(v[r]);
+    __syncthreads();
+    fft_reg<T>(v, slice, lg2, lt, true, tw2, 2 * F2);
+    // v[s] = conj(B[k1][n2]), n2 = lt + u sigma(s); store B e^{-2 pi i n2 k1 / P}
+    ColTw<T> ct;
+    const int u = F2 >> 4;
+    ct.init(reinterpret_cast<const cx<T>*>(g.tw), (int)g.P, k1, lt, u);
+    auto put = [&](auto lrc) {
+        constexpr int LR = decltype(lrc)::value;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int sigma = (s >> LR) + ((s & ((1 << LR) - 1)) << (4 - LR));
+            stg(row + lt + u * sigma, conj(cmul(v[s], slot_twiddle<LR, T>(ct, s))));
+        }
+    };
+    switch (fft_last_log_radix(lg2)) {
+    case 4: put(std::integral_constant<int, 4>{}); break;
+    case 3: put(std::integral_constant<int, 3>{}); break;
+    case 2: put(std::integral_constant<int, 2>{}); break;
+    default: put(std::integral_constant<int, 1>{}); break;
+    }
 }
 
-// second transform, column pass: input conj(A_t F(b~)_t)
+// Inverse column pass of the convolution: for column n2, the inverse L1-point
+// FFT over k1 of B'[k1][n2] (conjugate, forward FFT, conjugate) gives the
+// convolution at n1 L2 + n2; Z_s = c_s (a * b)_s / P for s < L goes to [P, P+L).
 template <typename T>
-__global__ void __launch_bounds__(128) k_bs_col2(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
+__global__ void __launch_bounds__(128) k_bs_col2inv(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
 {
     extern __shared__ unsigned char smem_raw[];
-    const Item it = items[blockIdx.x];
-    const ExecDesc& d = descs[it.desc];
-    const FftGeom& g = geom_of<T>(d);
-    cx<T>* base = bs_job<T>(d, g, it.a);
-    const int P = (int)g.P;
-    const cx<T>* bl = reinterpret_cast<const cx<T>*>(g.bl);
-    col_pass<T>(
-        reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw),
-        reinterpret_cast<const cx<T>*>(g.tw1), it.b,
-        [&](int t) { return conj(cmul(ldg(base + P + t), ldg(bl + t))); }, [&](int i, cx<T> v) { stg(base + i, v); });
-}
-
-// second transform, row pass: Z_s = c_s conj(E_s) / P for s < L, to [P, P+L)
-template <typename T>
-__global__ void __launch_bounds__(256) k_bs_row2(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
-{
-    extern __shared__ unsigned char smem_raw[];
-    const Item it = items[blockIdx.x];
+    const Item it = items[xcd_item(blockIdx.x, gridDim.x)];
     const ExecDesc& d = descs[it.desc];
     const FftGeom& g = geom_of<T>(d);
     cx<T>* base = bs_job<T>(d, g, it.a);
     const int P = (int)g.P, L = (int)g.L;
+    const int lg1 = g.logL1, lg2 = g.logL2;
+    const int F1 = 1 << lg1;
+    const int ltc = lg1 >= 11 ? 0 : 11 - lg1;  // TC = 2048 / F1 columns
+    const int tid = threadIdx.x;
+    const int c = tid & ((1 << ltc) - 1), lt = tid >> ltc;
+    const int n2 = (it.b << ltc) + c;
+    const int step = F1 >> 4;
     const cx<T>* chirp = reinterpret_cast<const cx<T>*>(g.chirp);
     const T invP = (T)1 / (T)P;
-    row_pass<T>(
-        reinterpret_cast<cx<T>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<T>*>(g.tw2), it.b,
-        [&](int i) { return ldg(base + i); },
-        [&](int s, cx<T> v) {
-            if (s < L) stg(base + P + s, cmul(ldg(chirp + s), cscale(conj(v), invP)));
-        });
+    cx<T> v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = conj(ldg(base + (((lt + r * step) << lg2) + n2)));
+    fft_reg<T>(v, reinterpret_cast<cx<T>*>(smem_raw) + c * slice_stride(F1), lg1, lt, true,
+               reinterpret_cast<const cx<T>*>(g.tw1), 2 * F1);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int t = (fft_out_index(s, lt, lg1) << lg2) + n2;
+        if (t < L) stg(base + P + t, cmul(ldg(chirp + t), cscale(conj(v[s]), invP)));
+    }
 }
 
 // Untangling of the length-2L real DFT from Z, summed over the jobs of the
@@ -917,9 +973,8 @@ cjt_status run(const Launch& L, const ExecDesc* dd, const Item* it, hipStream_t 
     case Kind::FftPass2: return go(k_pass2<T, K, kMulti>, L, s, dd, it, L.acc_off);
     case Kind::BsSingle: return go(k_bs_single<T, S, K>, L, s, dd, it, L.acc_off);
     case Kind::BsCol1: return go(k_bs_col1<T, S>, L, s, dd, it);
-    case Kind::BsRow1: return go(k_bs_row1<T>, L, s, dd, it);
-    case Kind::BsCol2: return go(k_bs_col2<T>, L, s, dd, it);
-    case Kind::BsRow2: return go(k_bs_row2<T>, L, s, dd, it);
+    case Kind::BsRowConv: return go(k_bs_rowconv<T>, L, s, dd, it);
+    case Kind::BsCol2Inv: return go(k_bs_col2inv<T>, L, s, dd, it);
     case Kind::BsUntangle: return go(k_bs_untangle<T, K, kMulti>, L, s, dd, it);
     case Kind::FftJobs: return go(k_single_job<T, S, K>, L, s, dd, it);
     case Kind::BsJobs: return go(k_bs_single_job<T, S, K>, L, s, dd, it);
@@ -1041,12 +1096,12 @@ cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sin
             const int TC = g.L1 >= 2048 ? 1 : 2048 / g.L1;
             const int TR = g.L2 >= 2048 ? 1 : 2048 / g.L2;
             const int nthr = TR * (g.L2 / 16);
-            const Kind ks[4] = {Kind::BsCol1, Kind::BsRow1, Kind::BsCol2, Kind::BsRow2};
-            for (int q = 0; q < 4; ++q) {
-                const bool col = (q % 2) == 0;
+            const Kind ks[3] = {Kind::BsCol1, Kind::BsRowConv, Kind::BsCol2Inv};
+            for (int q = 0; q < 3; ++q) {
+                const bool col = q != 1;
                 Bucket& b = bucket(ks[q], col ? 128 : nthr, name_cols);
                 const int tiles = col ? g.L2 / TC : g.L1 / TR;
-                if (q == 0) {  // tile-major, as the power-of-two column pass
+                if (col) {  // tile-major, as the power-of-two column pass
                     for (int t = 0; t < tiles; ++t)
                         for (int it = 0; it < jobs; ++it) b.items.push_back(Item{i, job_at(d, it, multi), t, 0});
                 } else {
@@ -1054,8 +1109,8 @@ cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sin
                         for (int t = 0; t < tiles; ++t) b.items.push_back(Item{i, j, t, 0});
                 }
                 b.lds = std::max(b.lds, col ? (size_t)TC * slice_stride(g.L1) * esz : (size_t)TR * slice_stride(g.L2) * esz);
-                b.flops += 0.125 * fl;
-                b.bytes += 0.125 * by;
+                b.flops += fl / 6.0;
+                b.bytes += by / 6.0;
             }
             Bucket& bu = bucket(Kind::BsUntangle, 256, name_rows);
             for (int64_t t = 0; t < (g.L / 2 + 1 + 255) / 256; ++t) bu.items.push_back(Item{i, 0, (int32_t)t, 0});
@@ -1072,9 +1127,8 @@ cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sin
         case Kind::FftSingle: sfx = "_single"; break;
         case Kind::BsSingle: sfx = "_bs_single"; break;
         case Kind::BsCol1:
-        case Kind::BsCol2: sfx = "_bs_cols"; break;
-        case Kind::BsRow1:
-        case Kind::BsRow2: sfx = "_bs_rows"; break;
+        case Kind::BsCol2Inv: sfx = "_bs_cols"; break;
+        case Kind::BsRowConv: sfx = "_bs_rows"; break;
         case Kind::BsUntangle: sfx = "_bs_untangle"; break;
         case Kind::FftJobs: sfx = "_jobs"; break;
         case Kind::BsJobs: sfx = "_bs_jobs"; break;
@@ -1085,8 +1139,8 @@ cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sin
     };
     // launch order: single-workgroup kinds, then the two-pass chains in dependency order
     const Kind order[] = {Kind::FftSingle, Kind::BsSingle, Kind::FftJobs, Kind::BsJobs,  Kind::JobReduce,
-                          Kind::FftPass1,  Kind::FftPass1Inv, Kind::FftPass2, Kind::BsCol1, Kind::BsRow1,
-                          Kind::BsCol2,    Kind::BsRow2,      Kind::BsUntangle};
+                          Kind::FftPass1,  Kind::FftPass1Inv, Kind::FftPass2, Kind::BsCol1, Kind::BsRowConv,
+                          Kind::BsCol2Inv, Kind::BsUntangle};
     for (Kind k : order) {
         for (auto& b : bk) {
             if (b.kind != k || b.items.empty()) continue;
@@ -1198,12 +1252,16 @@ __global__ void __launch_bounds__(128) k_bl_col(FftGeom g, cx<double>* scratch)
         reinterpret_cast<const cx<double>*>(g.tw1), blockIdx.x, [&](int64_t t) { return bl_input(chirp, L, P, t); }, [&](int64_t i, cx<double> v) { scratch[i] = v; });
 }
 
+// F(b~) stored row-major for the convolution row pass: frequency k1 + L1 k2 at
+// [k1][k2] = k1 L2 + k2.
 __global__ void __launch_bounds__(256) k_bl_row(FftGeom g, const cx<double>* scratch, cx<double>* bl)
 {
     extern __shared__ unsigned char smem_raw[];
+    const int64_t m1 = ((int64_t)1 << g.logL1) - 1;
     row_pass<double>(
         reinterpret_cast<cx<double>*>(smem_raw), g.logL1, g.logL2, reinterpret_cast<const cx<double>*>(g.tw2),
-        blockIdx.x, [&](int64_t i) { return scratch[i]; }, [&](int64_t i, cx<double> v) { bl[i] = v; });
+        blockIdx.x, [&](int64_t i) { return scratch[i]; },
+        [&](int64_t i, cx<double> v) { bl[((i & m1) << g.logL2) + (i >> g.logL1)] = v; });
 }
 
 namespace {
