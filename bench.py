@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the latency (N=1024), N=2^20 and uneven-batch (4096 instances) measurements")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the two-pass FFT splits for this batch before planning (schedule only)")
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="after timing, copy 256 MiB on the device (the counter calibration of the traffic summary)")
     ap.add_argument("--workload", choices=("batch", "serve"), default="batch",
@@ -290,6 +292,16 @@ def main():
     insts = inputs.batch_uniform_params(count, N, args.seed, r=1.0)
     log(f"bench: {count} transforms at N={N}")
 
+    tuned = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        tuned = [e.as_dict() for e in cjt.cjt_autotune(N, cjt.CJT_FP64, batch=count, reps=2)]
+        if not args.no_fp32:
+            tuned += [e.as_dict() for e in cjt.cjt_autotune(N, cjt.CJT_FP32_BULK, batch=count, reps=2)]
+        log(f"autotune ({time.perf_counter() - t0:.1f} s): " +
+            "; ".join(f"L={e['fft_len']} {'inv' if e['inverse'] else 'fwd'}{' fp32' if e['fp32'] else ''}: "
+                      f"2^{e['log2_cols_default']} cols {e['ms_default']:.2f} ms -> 2^{e['log2_cols_best']} "
+                      f"{e['ms_best']:.2f} ms" for e in tuned))
     t0 = time.perf_counter()
     plans64 = [cjt.cjt_plan(i.N, i.alpha, i.beta, 0, cjt.CJT_FP64) for i in insts]
     t_plan64 = time.perf_counter() - t0
@@ -407,6 +419,7 @@ def main():
         "p99_ms": float(np.percentile(r64["per"], 99)),
         "rel_error": err,
         "plan_s": {"fp64": t_plan64, "fp32_bulk": t_plan32},
+        "autotune": tuned,
         "kernels_ms_per_step": {k: v["total_ms"] / args.steps for k, v in kern.items()},
         "roofline": {"bound": "alu" if alu_bound else "hbm", "kernel": tname, "achieved": achieved,
                      "peak": ceiling, "unit": unit, "frac": achieved / ceiling, "traffic": traffic,

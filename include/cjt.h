@@ -102,6 +102,8 @@ typedef struct {
     int64_t fft_count_fwd;   /* Hahn-block transforms per forward call: M x nblocks */
     int64_t fft_count_inv;
     size_t device_bytes;     /* device memory held by the plan */
+    int32_t fft_log2_cols_fwd; /* two-pass split of the forward FFTs: log2 of the column length (0: one pass) */
+    int32_t fft_log2_cols_inv; /* the same for the inverse's length-2N FFTs */
 } cjt_plan_info;
 
 /* Create a plan for degree 1 <= N <= 2^21 (larger N return CJT_EUNSUPPORTED;
@@ -246,6 +248,43 @@ cjt_status cjt_server_drain(cjt_server_t s);
 cjt_status cjt_server_query(cjt_server_t s, cjt_server_stats* out, int reset);
 /* Drain, stop the threads and release everything. NULL is accepted. */
 cjt_status cjt_server_destroy(cjt_server_t s);
+
+/* ------------------------------------------------------------------ schedule autotuner
+ *
+ * FFTs longer than 4096 points run in two passes, L = L1 x L2 (column FFTs of
+ * length L1, row FFTs of length L2; chirp-z transforms split their
+ * power-of-two convolution length P the same way).  The split is a schedule
+ * choice: it changes occupancy and memory transactions, not the transform.
+ * The library keeps a table of splits keyed by (power-of-two length,
+ * inverse, chirp-z, precision); plans read it when they are created and keep
+ * the split they were made with.  Untuned lengths use L1 = 2^floor(lg/2).
+ * If CJT_TUNE_FILE names a file, it is loaded on first use. */
+typedef struct {
+    int64_t fft_len;            /* power-of-two length tuned (L, or P for chirp-z) */
+    int32_t inverse, chirp, fp32;
+    int32_t candidates;         /* splits timed */
+    int32_t log2_cols_default;  /* split before tuning */
+    int32_t log2_cols_best;     /* split now in the table */
+    double ms_default, ms_best; /* mean time of one batched call with each */
+} cjt_tune_entry;
+
+/* Times every accepted split of the two-pass FFTs that a plan of degree N
+ * uses (forward length N, inverse length 2N; lengths up to 4096 need none)
+ * on a synthetic plan (alpha = beta = 0.1, automatic M, the precision of
+ * `flags`: CJT_FP64 or CJT_FP32_BULK): `reps` batched calls of `batch`
+ * (1..4096) transforms of each direction per candidate on `stream`; stores the
+ * fastest in the table.  out receives one entry per tuned length (at most 2;
+ * *n_out of them).  Allocates and frees its own device buffers; returns after
+ * the device work completed. */
+cjt_status cjt_autotune(int64_t N, unsigned flags, int64_t batch, int reps, void* stream, cjt_tune_entry* out,
+                        int* n_out);
+/* Set one table entry (log2_cols = -1 removes it).  CJT_EINVAL for a length
+ * that runs in one pass or a split outside [max(4, lg-11), min(11, lg-4)]. */
+cjt_status cjt_tune_set(int64_t fft_len, int inverse, int chirp, int fp32, int log2_cols);
+/* Write / merge the table as text, one entry per line:
+ * "fft_len inverse chirp fp32 log2_cols" ('#' starts a comment).  Host only. */
+cjt_status cjt_tune_save(const char* path);
+cjt_status cjt_tune_load(const char* path);
 
 /* Describe a plan (host memory out). */
 cjt_status cjt_plan_query(cjt_plan_t plan, cjt_plan_info* out);

@@ -30,6 +30,7 @@ _EXPORTS = (
     "cjt_batch_create", "cjt_batch_execute", "cjt_batch_query", "cjt_batch_destroy",
     "cjt_server_create", "cjt_server_submit", "cjt_server_replay", "cjt_server_wait", "cjt_server_cancel",
     "cjt_server_pause", "cjt_server_drain", "cjt_server_query", "cjt_server_destroy",
+    "cjt_autotune", "cjt_tune_set", "cjt_tune_save", "cjt_tune_load",
 )
 
 
@@ -79,6 +80,8 @@ class cjt_plan_info(ctypes.Structure):
         ("fft_count_fwd", ctypes.c_int64),
         ("fft_count_inv", ctypes.c_int64),
         ("device_bytes", ctypes.c_size_t),
+        ("fft_log2_cols_fwd", ctypes.c_int32),
+        ("fft_log2_cols_inv", ctypes.c_int32),
     ]
 
 
@@ -124,6 +127,23 @@ class cjt_server_stats(ctypes.Structure):
         ("lat_p99_us", ctypes.c_double),
         ("lat_mean_us", ctypes.c_double),
         ("lat_max_us", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class cjt_tune_entry(ctypes.Structure):
+    _fields_ = [
+        ("fft_len", ctypes.c_int64),
+        ("inverse", ctypes.c_int32),
+        ("chirp", ctypes.c_int32),
+        ("fp32", ctypes.c_int32),
+        ("candidates", ctypes.c_int32),
+        ("log2_cols_default", ctypes.c_int32),
+        ("log2_cols_best", ctypes.c_int32),
+        ("ms_default", ctypes.c_double),
+        ("ms_best", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -182,6 +202,12 @@ def load(path=LIB_PATH):
         lib.cjt_server_drain.argtypes = [vp]
         lib.cjt_server_query.argtypes = [vp, P(cjt_server_stats), ci]
         lib.cjt_server_destroy.argtypes = [vp]
+        lib.cjt_autotune.argtypes = [i64, cu, i64, ci, vp, P(cjt_tune_entry), P(ci)]
+        lib.cjt_tune_set.argtypes = [i64, ci, ci, ci, ci]
+        lib.cjt_tune_save.argtypes = [ctypes.c_char_p]
+        lib.cjt_tune_load.argtypes = [ctypes.c_char_p]
+        for f in ("cjt_autotune", "cjt_tune_set", "cjt_tune_save", "cjt_tune_load"):
+            getattr(lib, f).restype = ci
         for f in ("cjt_plan", "cjt_forward", "cjt_inverse", "cjt_forward_batched", "cjt_inverse_batched",
                   "cjt_plan_query", "cjt_plan_describe", "cjt_plan_destroy", "cjt_batch_create",
                   "cjt_batch_execute", "cjt_batch_query", "cjt_batch_destroy", "cjt_server_create",
@@ -428,6 +454,28 @@ def cjt_server_query(server, reset=False):
 
 def cjt_server_destroy(server):
     server.destroy()
+
+
+def cjt_autotune(N, flags=CJT_FP64, batch=1, reps=3, stream=None):
+    """Time the two-pass splits of a plan of degree N (batched calls of `batch`
+    transforms) and keep the fastest; returns the entries."""
+    arr = (cjt_tune_entry * 2)()
+    n = ctypes.c_int(0)
+    _check(load().cjt_autotune(int(N), int(flags), int(batch), int(reps), _stream(stream), arr, ctypes.byref(n)),
+           "cjt_autotune")
+    return [arr[i] for i in range(n.value)]
+
+
+def cjt_tune_set(fft_len, inverse, chirp, fp32, log2_cols):
+    _check(load().cjt_tune_set(int(fft_len), int(inverse), int(chirp), int(fp32), int(log2_cols)), "cjt_tune_set")
+
+
+def cjt_tune_save(path):
+    _check(load().cjt_tune_save(os.fsencode(path)), "cjt_tune_save")
+
+
+def cjt_tune_load(path):
+    _check(load().cjt_tune_load(os.fsencode(path)), "cjt_tune_load")
 
 
 def cjt_plan_query(plan):

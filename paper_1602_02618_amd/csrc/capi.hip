@@ -246,6 +246,11 @@ void describe(const Plan& P, cjt_plan_info* out)
     out->fft_count_fwd = (int64_t)P.fwd.nblk * P.fwd.M;
     out->fft_count_inv = (int64_t)P.inv.nblk * P.inv.M;
     out->device_bytes = P.arena_bytes;
+    FftGeom g;
+    geometry_shape(P.N, &g, P.lg1_f);
+    out->fft_log2_cols_fwd = g.single ? 0 : g.logL1;
+    geometry_shape(2 * P.N, &g, P.lg1_i);
+    out->fft_log2_cols_inv = g.single ? 0 : g.logL1;
 }
 
 }  // namespace
@@ -538,6 +543,92 @@ cjt_status cjt_batch_destroy(cjt_batch_t batch)
     CJT_HIP_TRY(hipDeviceSynchronize());
     batch_free(batch);
     return CJT_OK;
+}
+
+cjt_status cjt_autotune(int64_t N, unsigned flags, int64_t batch, int reps, void* stream, cjt_tune_entry* out,
+                        int* n_out)
+{
+    if (!out || !n_out) return fail(CJT_EINVAL, "null output");
+    *n_out = 0;
+    if (reps < 1 || reps > 1000) return fail(CJT_EINVAL, "reps must be in [1, 1000]");
+    if (batch < 1 || batch > 4096) return fail(CJT_EINVAL, "batch must be in [1, 4096]");
+    const unsigned prec = flags & CJT_FP32_BULK;
+    if (flags & ~(unsigned)CJT_FP32_BULK) return fail(CJT_EINVAL, "flags must be CJT_FP64 or CJT_FP32_BULK");
+    const double a = 0.1, b = 0.1;
+    cjt_status s = check_args(N, a, b, 0, prec);
+    if (s != CJT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    CJT_HIP_TRY(hipGetDevice(&dev));
+    // synthetic input c_n = 1/(n+1) and an output buffer
+    const size_t n1 = (size_t)N + 1, total = n1 * (size_t)batch;
+    std::vector<double> host(total);
+    for (size_t i = 0; i < total; ++i) host[i] = 1.0 / (double)(i % n1 + 1);
+    double* buf = nullptr;
+    if (hipMalloc((void**)&buf, sizeof(double) * 2 * total) != hipSuccess)
+        return fail(CJT_ENOMEM, "autotune buffers");
+    double* d_in = buf;
+    double* d_out = buf + total;
+    std::vector<int64_t> offs((size_t)batch);
+    for (int64_t i = 0; i < batch; ++i) offs[(size_t)i] = i * (int64_t)n1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    s = CJT_OK;
+    if (hipMemcpy(d_in, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        s = fail(CJT_EDEVICE, "autotune set-up");
+    for (int inv = 0; inv < 2 && s == CJT_OK; ++inv) {
+        const int64_t L = inv ? 2 * N : N;
+        FftGeom g;
+        geometry_shape(L, &g, -1);
+        if (g.single) continue;
+        const int64_t F = fft_power_length(L);
+        const int lg = g.bluestein ? g.logP : g.logL;
+        int lo = 0, hi = 0;
+        split_range(lg, &lo, &hi);
+        const bool chirp = g.bluestein != 0;
+        cjt_tune_entry e{};
+        e.fft_len = F;
+        e.inverse = inv;
+        e.chirp = chirp ? 1 : 0;
+        e.fp32 = prec ? 1 : 0;
+        e.log2_cols_default = tuned_split(F, prec != 0, chirp, inv != 0);
+        if (e.log2_cols_default < 0) e.log2_cols_default = lg / 2;
+        double best = 1e300;
+        for (int lg1 = lo; lg1 <= hi && s == CJT_OK; ++lg1) {
+            set_tuned_split(F, prec != 0, chirp, inv != 0, lg1);
+            Plan P;
+            plan_host(&P, N, a, b, 0, prec);
+            P.device = dev;
+            if ((s = build_plan_device(&P, st, nullptr, nullptr)) != CJT_OK) break;
+            float ms = 0.0f;
+            const std::vector<const Plan*> plans((size_t)batch, &P);
+            if ((s = execute(inv != 0, plans, offs, d_in, d_out, st)) == CJT_OK &&
+                hipEventRecord(e0, st) == hipSuccess) {
+                for (int r = 0; r < reps && s == CJT_OK; ++r) s = execute(inv != 0, plans, offs, d_in, d_out, st);
+                if (s == CJT_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    s = fail(CJT_EDEVICE, "autotune timing");
+            }
+            (void)hipStreamSynchronize(st);
+            if (P.arena && P.own_arena) (void)hipFree(P.arena);
+            if (s != CJT_OK) break;
+            const double t = (double)ms / reps;
+            e.candidates += 1;
+            if (lg1 == e.log2_cols_default) e.ms_default = t;
+            if (t < best) {
+                best = t;
+                e.log2_cols_best = lg1;
+                e.ms_best = t;
+            }
+        }
+        set_tuned_split(F, prec != 0, chirp, inv != 0, s == CJT_OK ? e.log2_cols_best : -1);
+        if (s == CJT_OK && *n_out < 2) out[(*n_out)++] = e;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    return s;
 }
 
 }  // extern "C"

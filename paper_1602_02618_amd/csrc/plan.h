@@ -49,6 +49,9 @@ struct Plan {
     // complex FFT geometries of the two grids, FP64 (geo_*) and in the
     // precision of the Hahn-block FFTs (geob_*); chirp-z tables in the arena
     FftGeom geo_f{}, geo_i{}, geob_f{}, geob_i{};
+    // log2 of the column length of the two-pass FFTs of the forward (N) and
+    // inverse (2N) grids, from the schedule table at planning time (-1: default)
+    int lg1_f = -1, lg1_i = -1;
 };
 
 constexpr int kRecWidthFwd = 64 * 4;    // points per forward recurrence task (4 per lane)
@@ -68,11 +71,21 @@ void plan_layout(Plan* P);
 // `scratch` (scratch_bytes); either may be null, then it is allocated here
 // (the arena is then owned by the plan).  Returns after the work completed.
 cjt_status build_plan_device(Plan* P, hipStream_t st, void* arena, void* scratch);
-// Shape of a length-L complex FFT without tables.
-void geometry_shape(int64_t L, FftGeom* g);
+// Shape of a length-L complex FFT without tables; lg1 is the log2 column
+// length of a two-pass split (-1 or out of range: half the length's bits).
+void geometry_shape(int64_t L, FftGeom* g, int lg1);
+// Power-of-two length the FFT of length L runs at (L, or P for chirp-z).
+int64_t fft_power_length(int64_t L);
+// Accepted lg1 range of a two-pass split of a length 2^lg.
+void split_range(int lg, int* lo, int* hi);
+// Schedule table (csrc/tune.hip): tuned lg1 of the two-pass FFT of power-of-two
+// length F for a precision, chirp-z or direct, forward or inverse Hahn blocks;
+// -1 when untuned.
+int tuned_split(int64_t F, bool fp32, bool chirp, bool inverse);
+void set_tuned_split(int64_t F, bool fp32, bool chirp, bool inverse, int lg1);
 // Shape plus tables: shared power-of-two twiddles; for lengths that are not
 // powers of two, chirp-z tables built into mem (chirp_table_bytes) with
 // scratch (chirp_scratch_bytes), asynchronously on st.
-cjt_status fft_geometry(int64_t L, bool fp32, hipStream_t st, FftGeom* g, char* mem, char* scratch);
+cjt_status fft_geometry(int64_t L, bool fp32, hipStream_t st, FftGeom* g, char* mem, char* scratch, int lg1);
 
 }  // namespace cjt

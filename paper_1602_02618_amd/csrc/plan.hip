@@ -448,8 +448,8 @@ Layout layout_of(const Plan& P)
     l.Ti = take(sizeof(RecTask) * std::max<size_t>(1, P.tasks_i.size()));
     l.Mu = take(sizeof(double) * ni);
     FftGeom gf, gi;
-    geometry_shape(N, &gf);
-    geometry_shape(2 * N, &gi);
+    geometry_shape(N, &gf, P.lg1_f);
+    geometry_shape(2 * N, &gi, P.lg1_i);
     l.Gf = take(gf.bluestein ? chirp_table_bytes(gf, false) : 0);
     l.Gi = take(gi.bluestein ? chirp_table_bytes(gi, false) : 0);
     l.Gbf = take(fp32 && gf.bluestein ? chirp_table_bytes(gf, true) : 0);
@@ -475,14 +475,29 @@ cjt_status weights_program(const Plan& P, const FftGeom& gi, Program* pr)
 
 }  // namespace
 
+int64_t fft_power_length(int64_t L)
+{
+    FftGeom g;
+    geometry_shape(L, &g, -1);
+    return g.bluestein ? g.P : g.L;
+}
+
 void plan_layout(Plan* P)
 {
+    // two-pass splits from the schedule table (the library default where untuned)
+    const bool fp32 = (P->flags & CJT_FP32_BULK) != 0;
+    {
+        FftGeom g;
+        geometry_shape(P->N, &g, -1);
+        P->lg1_f = tuned_split(fft_power_length(P->N), fp32, g.bluestein != 0, false);
+        geometry_shape(2 * P->N, &g, -1);
+        P->lg1_i = tuned_split(fft_power_length(2 * P->N), fp32, g.bluestein != 0, true);
+    }
     const Layout l = layout_of(*P);
     P->arena_bytes = l.total;
     FftGeom gf, gi;
-    geometry_shape(P->N, &gf);
-    geometry_shape(2 * P->N, &gi);
-    const bool fp32 = (P->flags & CJT_FP32_BULK) != 0;
+    geometry_shape(P->N, &gf, P->lg1_f);
+    geometry_shape(2 * P->N, &gi, P->lg1_i);
     size_t scr = 0;
     for (const FftGeom* g : {&gf, &gi})
         if (g->bluestein) scr = std::max(scr, chirp_scratch_bytes(*g, fp32));
@@ -530,13 +545,13 @@ cjt_status build_plan_device(Plan* P, hipStream_t st, void* arena, void* scratch
     std::vector<double> hmu;
     do {
         // FFT geometries of both grids; chirp-z tables live in the arena
-        if ((stt = fft_geometry(N, false, st, &P->geo_f, base + ly.Gf, scr)) != CJT_OK) break;
-        if ((stt = fft_geometry(2 * N, false, st, &P->geo_i, base + ly.Gi, scr)) != CJT_OK) break;
+        if ((stt = fft_geometry(N, false, st, &P->geo_f, base + ly.Gf, scr, P->lg1_f)) != CJT_OK) break;
+        if ((stt = fft_geometry(2 * N, false, st, &P->geo_i, base + ly.Gi, scr, P->lg1_i)) != CJT_OK) break;
         P->geob_f = P->geo_f;
         P->geob_i = P->geo_i;
         if (fp32) {
-            if ((stt = fft_geometry(N, true, st, &P->geob_f, base + ly.Gbf, scr)) != CJT_OK) break;
-            if ((stt = fft_geometry(2 * N, true, st, &P->geob_i, base + ly.Gbi, scr)) != CJT_OK) break;
+            if ((stt = fft_geometry(N, true, st, &P->geob_f, base + ly.Gbf, scr, P->lg1_f)) != CJT_OK) break;
+            if ((stt = fft_geometry(2 * N, true, st, &P->geob_i, base + ly.Gbi, scr, P->lg1_i)) != CJT_OK) break;
         }
         const double a = P->alpha, b = P->beta;
         const unsigned bs = 256;
@@ -624,17 +639,28 @@ int ilog2_ceil(int64_t x)
     return lg;
 }
 
-void split(FftGeom* g, int lg, int64_t F)
+void split(FftGeom* g, int lg, int64_t F, int lg1)
 {
     g->single = F <= kSingleMax ? 1 : 0;
     if (!g->single) {
-        g->logL1 = lg / 2;
+        int lo = 0, hi = 0;
+        split_range(lg, &lo, &hi);
+        g->logL1 = lg1 >= lo && lg1 <= hi ? lg1 : lg / 2;
         g->logL2 = lg - g->logL1;
         g->L1 = 1 << g->logL1;
         g->L2 = 1 << g->logL2;
     }
 }
 }  // namespace
+
+// Column lengths 2^lg1 the two-pass kernels accept for a length 2^lg: at
+// least 16 and at most 2048 points on either side (16 values per thread, at
+// most 2048 points per workgroup pass).
+void split_range(int lg, int* lo, int* hi)
+{
+    *lo = std::max(4, lg - 11);
+    *hi = std::min(11, lg - 4);
+}
 
 // Twiddles e^{i pi q / F}, q < 2F, of a power-of-two length F, built once per
 // (device, F, precision) and kept for the life of the process (at most one
@@ -661,25 +687,25 @@ cjt_status fft_twiddles_cached(int64_t F, bool fp32, hipStream_t st, const void*
 // Shape of the length-L complex FFT: power-of-two lengths run directly (one
 // or two passes), every other length through the chirp-z convolution of
 // power-of-two length P >= 2L - 1.
-void geometry_shape(int64_t L, FftGeom* g)
+void geometry_shape(int64_t L, FftGeom* g, int lg1)
 {
     *g = FftGeom{};
     g->L = L;
     g->logL = ilog2_ceil(L);
     if ((L & (L - 1)) == 0) {
-        split(g, g->logL, L);
+        split(g, g->logL, L, lg1);
     } else {
         g->bluestein = 1;
         g->logP = ilog2_ceil(2 * L - 1);
         g->P = (int64_t)1 << g->logP;
-        split(g, g->logP, g->P);
+        split(g, g->logP, g->P, lg1);
     }
 }
 
-cjt_status fft_geometry(int64_t L, bool fp32, hipStream_t st, FftGeom* g, char* mem, char* scratch)
+cjt_status fft_geometry(int64_t L, bool fp32, hipStream_t st, FftGeom* g, char* mem, char* scratch, int lg1)
 {
     if (L < 1) return fail(CJT_EINVAL, "FFT length must be positive");
-    geometry_shape(L, g);
+    geometry_shape(L, g, lg1);
     const int64_t F = g->bluestein ? g->P : L;
     cjt_status s = fft_twiddles_cached(F, fp32, st, &g->tw);
     if (s != CJT_OK) return s;

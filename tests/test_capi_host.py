@@ -155,3 +155,40 @@ def test_stirling_coefficients_match_gamma():
     ser = mp.fsum(mp.mpf(a[k].numerator) / a[k].denominator / z ** k for k in range(17))
     assert abs(ser / ref - 1) < 1e-22
     assert str(a[1]) == "1/12" and str(a[2]) == "1/288" and str(a[3]) == "-139/51840"
+
+
+def test_schedule_table_host(lib, tmp_path):
+    """The split table: validation, effect on plan descriptions (host only),
+    save and load."""
+    N = 65536  # forward FFT length 65536 = 2^16 (two passes), inverse 2^17
+    d0 = lib.cjt_plan_describe(N, 0.1, 0.2)
+    assert d0.fft_log2_cols_fwd == 8 and d0.fft_log2_cols_inv == 8  # default: floor(lg / 2)
+    for bad in ((4096, 0, 0, 0, 6), (65536, 0, 0, 0, 3), (65536, 0, 0, 0, 13), (65537, 0, 0, 0, 8)):
+        with pytest.raises(lib.CJTError) as e:
+            lib.cjt_tune_set(*bad)
+        assert e.value.status == lib.CJT_EINVAL
+    try:
+        lib.cjt_tune_set(65536, 0, 0, 0, 5)
+        lib.cjt_tune_set(1 << 17, 1, 0, 0, 11)
+        d1 = lib.cjt_plan_describe(N, 0.1, 0.2)
+        assert d1.fft_log2_cols_fwd == 5 and d1.fft_log2_cols_inv == 11
+        assert lib.cjt_plan_describe(N, 0.1, 0.2, 0, lib.CJT_FP32_BULK).fft_log2_cols_fwd == 8  # other precision
+        path = str(tmp_path / "sched.txt")
+        lib.cjt_tune_save(path)
+        lines = [l.split() for l in open(path) if not l.startswith("#")]
+        assert ["65536", "0", "0", "0", "5"] in lines and ["131072", "1", "0", "0", "11"] in lines
+        lib.cjt_tune_set(65536, 0, 0, 0, -1)
+        lib.cjt_tune_set(1 << 17, 1, 0, 0, -1)
+        assert lib.cjt_plan_describe(N, 0.1, 0.2).fft_log2_cols_fwd == 8
+        lib.cjt_tune_load(path)
+        assert lib.cjt_plan_describe(N, 0.1, 0.2).fft_log2_cols_fwd == 5
+        # chirp-z lengths are keyed by their convolution length: N = 70000 -> P = 2^18
+        lib.cjt_tune_set(1 << 18, 0, 1, 0, 7)
+        assert lib.cjt_plan_describe(70000, 0.1, 0.2).fft_log2_cols_fwd == 7
+        bad = tmp_path / "bad.txt"
+        bad.write_text("65536 0 0 0 99\n")
+        with pytest.raises(lib.CJTError):
+            lib.cjt_tune_load(str(bad))
+    finally:
+        for key in ((65536, 0, 0, 0), (1 << 17, 1, 0, 0), (1 << 18, 0, 1, 0)):
+            lib.cjt_tune_set(*key, -1)
