@@ -146,6 +146,36 @@ __device__ __forceinline__ void dft(cx<T>* v)
     else dft16(v);
 }
 
+// Multiplies v[r] (r = 1..R-1) by the stage twiddles w^{r k}, w^k = tw[k twmul].
+// Radix 8 and 16 form them from two table reads, w^k and w^{4k}, as
+// (w^{4k})^(r/4) (w^k)^(r mod 4); lower radices read each one.
+template <typename T, int R>
+__device__ __forceinline__ void twiddle_stage(cx<T>* v, const cx<T>* __restrict__ tw, int k, int twmul)
+{
+    if constexpr (R <= 4) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], ldg(tw + (r * k) * twmul));
+    } else {
+        const cx<T> b1 = ldg(tw + k * twmul);
+        const cx<T> b4 = ldg(tw + (4 * k) * twmul);
+        const cx<T> b2 = cmul(b1, b1), b3 = cmul(b2, b1);
+        const cx<T> p[4] = {cx<T>{(T)1, (T)0}, b1, b2, b3};
+        cx<T> a[R / 4];
+        a[0] = cx<T>{(T)1, (T)0};
+        a[1] = b4;
+        if constexpr (R == 16) {
+            a[2] = cmul(b4, b4);
+            a[3] = cmul(a[2], b4);
+        }
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            if ((r & 3) == 0) v[r] = cmul(v[r], a[r >> 2]);
+            else if (r < 4) v[r] = cmul(v[r], p[r]);
+            else v[r] = cmul(v[r], cmul(a[r >> 2], p[r & 3]));
+        }
+    }
+}
+
 // One Stockham stage of radix R for an F-point transform at buf[base .. base+F)
 // (padded indices).  `lt` is the thread's index among the F/16 threads that
 // serve this transform (or 0 when F < 16), BPT = butterflies per thread.
@@ -175,10 +205,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int F, int Ns, int lt, int
         for (int q = 0; q < BPT; ++q) {
             int j = lt + q * stride;
             int k = j & (Ns - 1);
-            if (Ns > 1) {
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], ldg(tw + (r * k) * twmul));
-            }
+            if (Ns > 1) twiddle_stage<T, R>(v[q], tw, k, twmul);
             dft<T, R>(v[q]);
             int idxD = (j - k) * R + k;
 #pragma unroll
@@ -271,8 +298,7 @@ __device__ __forceinline__ void fft_reg_last(cx<T> (&v)[16], const cx<T>* buf, i
         for (int r = 0; r < R; ++r) w[r] = buf[lds_pad(j + r * FR)];
 #pragma unroll
         for (int r = 0; r < R; ++r) lds_pin(w[r]);
-#pragma unroll
-        for (int r = 1; r < R; ++r) w[r] = cmul(w[r], ldg(tw + (r * k) * twmul));
+        twiddle_stage<T, R>(w, tw, k, twmul);
         dft<T, R>(w);
 #pragma unroll
         for (int r = 0; r < R; ++r) v[q * R + r] = w[r];
