@@ -183,13 +183,20 @@ void build_tasks(const Part& P, int width, std::vector<RecTask>* out, int64_t* p
 
 // ------------------------------------------------------------------ M selection
 
-// Predicted cost of one forward plus one inverse transform for a given M:
-// Hahn blocks cost one complex FFT of length L per (block, term) and the
-// recurrence a few FP64 operations per (point, degree) pair.
+// Predicted GPU cost of one forward plus one inverse transform for a given M:
+// Hahn blocks cost one complex FFT of length L per (block, term), counted as
+// 5 L log2 L, and the recurrence a weight per (point, degree) pair.  The
+// weight is calibrated on MI355X step times of batched transforms: one
+// pair costs about as much as one FFT "flop" (the FFT passes move their
+// intermediates through memory while the recurrences run from registers on a
+// concurrent stream), which puts the optimum at M = 7-8 for N up to 2e5.  Very
+// large degrees usually run in small batches, where the recurrences' serial
+// chains are exposed; above N = 2^18 their weight grows to 3.5 at N = 2^20.
 static double plan_cost(int64_t N, const Part& f, const Part& i)
 {
     auto fft = [](double L) { return 5.0 * L * log2(fmax(L, 2.0)); };
-    const double rec = 8.0;
+    const double big = log2((double)N / 262144.0);
+    const double rec = big > 0.0 ? 1.0 + 1.25 * big : 1.0;
     return f.nblk * f.M * fft((double)N) + i.nblk * i.M * fft(2.0 * (double)N) +
            rec * (double)(f.rec_entries + i.rec_entries);
 }
