@@ -73,7 +73,7 @@ struct ExecDesc {
     int64_t deg_lo[kMaxBlocks], deg_hi[kMaxBlocks];  // half-open degree ranges of the blocks
     int64_t win_lo[kMaxBlocks], win_hi[kMaxBlocks];  // inclusive grid windows of the blocks
     const double* C;          // [M][N+1]   Hahn coefficients C_{n,m}
-    const cx<double>* uv;     // [M][G+1]   (u_m, v_m) at the grid points
+    const cx<double>* uv;     // [M][G+1]   (u_m, v_m) at the grid points; inverse: planes (u_m+v_m)/2, (u_m-v_m)/2
     const double* w;          // [2N+1]     Clenshaw--Curtis weights (inverse)
     const double* s;          // [N+1]      1 / A_n (inverse)
     const RecTask* tasks;     // [ntasks]   recurrence tasks, longest first

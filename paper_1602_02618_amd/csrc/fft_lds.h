@@ -33,6 +33,17 @@ __device__ __forceinline__ void lds_pin(cx<T>& a)
     asm volatile("" : "+v"(a.re), "+v"(a.im));
 }
 
+// A per-thread index the compiler cannot see through.  Taken at the top of
+// a loop body, it keeps the addresses derived from the index (loads, LDS
+// exchanges, stores: dozens of 64-bit values in an unrolled transform) from
+// being hoisted out of the loop and held in registers across all of its
+// iterations, which costs waves per SIMD.
+__device__ __forceinline__ int opaque(int x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
 
 // Distance between the LDS slices of consecutive transforms of length F: the

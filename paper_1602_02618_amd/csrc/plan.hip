@@ -311,13 +311,30 @@ __global__ void k_plan_C(int64_t N, double a, double b, int M, int64_t nlo, Term
 // with theta_{m,l} = (a + l + 1/2) pi/2 - (a + b + m + 1) theta/2 (Sec. 2.1, eq. Jacasyuv):
 // = K c^-m e^{i phi_0} e^{-i m theta/2} sum_l a_l b_{m-l} (i t)^l,
 //   t = cot(theta/2), K = s^-(a+1/2) c^-(b+1/2), phi_0 = (a+1/2) pi/2 - (a+b+1) theta/2.
+//
+// The forward blocks take (u_m, v_m) interleaved.  The transposed blocks of
+// the inverse (halves = true) take, per term, the two planes
+// S = (u_m + v_m)/2 and D = (u_m - v_m)/2 of G+1 values each, stored back to
+// back in the same G+1 complex slots: the real-input FFT's r is then one
+// product per element, r_j = S_j g_j and r_{2G-j} = D_j g_j.
+__device__ __forceinline__ void put_uv(cx<double>* uv, int64_t G, int m, int64_t i, double u, double v, bool halves)
+{
+    if (!halves) {
+        uv[(int64_t)m * (G + 1) + i] = {u, v};
+        return;
+    }
+    double* S = reinterpret_cast<double*>(uv + (int64_t)m * (G + 1));
+    S[i] = 0.5 * (u + v);
+    S[G + 1 + i] = 0.5 * (u - v);
+}
+
 __global__ void k_plan_uv(int64_t G, double a, double b, int M, int64_t lo, int64_t hi, TermScale ts,
-                          cx<double>* uv)
+                          cx<double>* uv, bool halves)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i > G) return;
     if (i < lo || i > hi || i <= 0 || i >= G) {
-        for (int m = 0; m < M; ++m) uv[(int64_t)m * (G + 1) + i] = {0.0, 0.0};
+        for (int m = 0; m < M; ++m) put_uv(uv, G, m, i, 0.0, 0.0, halves);
         return;
     }
     double ca[kMaxM + 1], cb[kMaxM + 1];
@@ -354,7 +371,7 @@ __global__ void k_plan_uv(int64_t G, double a, double b, int M, int64_t lo, int6
         const double ei = e0s * rc - e0c * rs;
         const double vr = cm * (er * wr - ei * wi);
         const double vi = cm * (er * wi + ei * wr);
-        uv[(int64_t)m * (G + 1) + i] = {ldexp(vr, -ts.e[m]), ldexp(vi, -ts.e[m])};
+        put_uv(uv, G, m, i, ldexp(vr, -ts.e[m]), ldexp(vi, -ts.e[m]), halves);
         cm *= ic;
     }
 }
@@ -571,9 +588,9 @@ cjt_status build_plan_device(Plan* P, hipStream_t st, void* arena, void* scratch
         const TermScale ts = term_scale(*P);
         hipLaunchKernelGGL(k_plan_C, grid(nf), dim3(bs), 0, st, N, a, b, M, nlo, ts, P->C);
         const int64_t flo = P->fwd.nblk ? P->fwd.win_lo[0] : 1, fhi = P->fwd.nblk ? P->fwd.win_hi[0] : 0;
-        hipLaunchKernelGGL(k_plan_uv, grid(nf), dim3(bs), 0, st, N, a, b, P->fwd.M, flo, fhi, ts, P->uv_f);
+        hipLaunchKernelGGL(k_plan_uv, grid(nf), dim3(bs), 0, st, N, a, b, P->fwd.M, flo, fhi, ts, P->uv_f, false);
         const int64_t ilo = P->inv.nblk ? P->inv.win_lo[0] : 1, ihi = P->inv.nblk ? P->inv.win_hi[0] : 0;
-        hipLaunchKernelGGL(k_plan_uv, grid(ni), dim3(bs), 0, st, 2 * N, a, b, P->inv.M, ilo, ihi, ts, P->uv_i);
+        hipLaunchKernelGGL(k_plan_uv, grid(ni), dim3(bs), 0, st, 2 * N, a, b, P->inv.M, ilo, ihi, ts, P->uv_i, true);
         hipLaunchKernelGGL(k_plan_s, grid(nf), dim3(bs), 0, st, N, a, b, P->s);
         if (hipGetLastError() != hipSuccess) {
             stt = fail(CJT_EDEVICE, "plan kernel launch failed");

@@ -58,67 +58,56 @@ template <>
 struct Source<Src::FwdAsy> {
     // job = k * M + m
     static constexpr bool kMulti = true;
+    // Branch-free: one pair of loads at an always valid address, masked by
+    // the block's degree range, so all loads of a thread issue back to back.
     __device__ static cx<double> load(const ExecDesc& d, int job, int t)
     {
         const int k = job / d.M, m = job - k * d.M;
         const int lo = (int)d.deg_lo[k], hi = (int)d.deg_hi[k];
+        const int N = (int)d.N;
         const int n0 = 2 * t, n1 = n0 + 1;
+        const int c0 = min(n0, N - 1);  // pair (c0, c0 + 1) within [0, N]
         const double* Cm = d.C + (int64_t)m * (d.N + 1);
-        const bool a0 = in_range(n0, lo, hi), a1 = in_range(n1, lo, hi);
-        if (a0 && a1) {  // both degrees present (n1 <= N): one pair of loads each
-            const dpair8 c = ldg_pair(Cm + n0), x = ldg_pair(d.in + n0);
-            return {c.x * x.x, c.y * x.y};
-        }
-        return {a0 ? ldg(Cm + n0) * ldg(d.in + n0) : 0.0, a1 ? ldg(Cm + n1) * ldg(d.in + n1) : 0.0};
+        const dpair8 c = ldg_pair(Cm + c0), x = ldg_pair(d.in + c0);
+        const double v0 = n0 == c0 ? c.x * x.x : c.y * x.y;  // n0 = N reads the upper element
+        const double v1 = c.y * x.y;
+        return {in_range(n0, lo, hi) ? v0 : 0.0, in_range(n1, lo, hi) ? v1 : 0.0};
     }
 };
 
 template <>
 struct Source<Src::InvAsy> {
     static constexpr bool kMulti = true;
-    // a_j = u_m(theta_j) g_j, b_j = v_m(theta_j) g_j on the window (zero elsewhere);
-    // r_0 = a_0, r_G = a_G, r_j = (a_j + b_j)/2 and r_{2G-j} = (a_j - b_j)/2 for 0 < j < G.
-    __device__ static double r1(int G, double g, cx<double> uv, int j, bool mirror)
-    {
-        if (j == 0 || j == G) return uv.re * g;
-        return 0.5 * g * (mirror ? uv.re - uv.im : uv.re + uv.im);
-    }
+    // With a_j = u_m(theta_j) g_j and b_j = v_m(theta_j) g_j on the window (zero
+    // elsewhere): r_0 = a_0, r_G = a_G, r_j = (a_j + b_j)/2 and
+    // r_{2G-j} = (a_j - b_j)/2 for 0 < j < G.  The plan stores the halved sum and
+    // difference of (u_m, v_m) as two planes S and D of G+1 values (both ends
+    // are outside every window, where u_m = v_m = 0), so r_j = S_j g_j for
+    // j <= G and r_{2G-j} = D_j g_j.
     __device__ static cx<double> load(const ExecDesc& d, int job, int t)
     {
         const int k = job / d.M;
         return pair(d, k, job - k * d.M, t);
     }
-    // (r_q, r_{q+1}) of term m on block k's window for q = 2t.  q <= G - 1
-    // reads points q, q+1; q >= G + 1 reads 2G - q - 1, 2G - q (the mirror);
-    // q = G straddles the two halves.
+    // (r_q, r_{q+1}) of term m on block k's window for q = 2t.  Both come from
+    // the adjacent points jl, jl + 1: q < G takes S at q, q+1; q >= G takes D at
+    // the mirrors 2G-q, 2G-q-1 (D_G = S_G = 0 covers q = G).  Two pair loads at
+    // always valid addresses, then masks; the S pair is 16-byte aligned (q even)
+    // and so is the D pair (G even, jl odd, plane offset G+1).
     __device__ static cx<double> pair(const ExecDesc& d, int k, int m, int t)
     {
         const int lo = (int)d.win_lo[k], hi = (int)d.win_hi[k] + 1;
-        const cx<double>* uvm = d.uv + (int64_t)m * (d.G + 1);
         const int G = (int)d.G;
+        const double* S = reinterpret_cast<const double*>(d.uv + (int64_t)m * (G + 1));
         const int q = 2 * t;
-        if (q + 1 <= G || q > G) {
-            const bool mirror = q > G;
-            const int j0 = mirror ? 2 * G - q : q;    // point of r_q
-            const int j1 = mirror ? j0 - 1 : j0 + 1;  // point of r_{q+1}
-            const int jl = mirror ? j1 : j0;          // lower of the two
-            const bool a0 = in_range(j0, lo, hi), a1 = in_range(j1, lo, hi);
-            if (!a0 && !a1) return {0.0, 0.0};
-            if (a0 && a1) {
-                const dpair8 g = ldg_pair(d.p + jl);
-                const cx<double> ua = ldg(uvm + jl), ub = ldg(uvm + jl + 1);
-                const double g0 = mirror ? g.y : g.x, g1 = mirror ? g.x : g.y;
-                const cx<double> u0 = mirror ? ub : ua, u1 = mirror ? ua : ub;
-                return {r1(G, g0, u0, j0, mirror), r1(G, g1, u1, j1, mirror)};
-            }
-            const int j = a0 ? j0 : j1;
-            const double v = r1(G, ldg(d.p + j), ldg(uvm + j), j, mirror);
-            return a0 ? cx<double>{v, 0.0} : cx<double>{0.0, v};
-        }
-        // q = G (G even): r_G from point G, r_{G+1} from point G - 1 (mirrored)
-        const bool a0 = in_range(G, lo, hi), a1 = in_range(G - 1, lo, hi);
-        return {a0 ? r1(G, ldg(d.p + G), ldg(uvm + G), G, false) : 0.0,
-                a1 ? r1(G, ldg(d.p + G - 1), ldg(uvm + G - 1), G - 1, true) : 0.0};
+        const bool upper = q >= G;
+        const int jl = upper ? 2 * G - q - 1 : q;  // in [0, G - 1]
+        const dpair8 g = ldg_pair(d.p + jl);
+        const dpair8 w = ldg_pair(S + (upper ? G + 1 : 0) + jl);
+        const double a0 = w.x * g.x, a1 = w.y * g.y;  // at points jl, jl + 1
+        const int j0 = upper ? jl + 1 : jl, j1 = upper ? jl : jl + 1;
+        const double r0 = upper ? a1 : a0, r1 = upper ? a0 : a1;
+        return {in_range(j0, lo, hi) ? r0 : 0.0, in_range(j1, lo, hi) ? r1 : 0.0};
     }
 };
 
@@ -471,25 +460,27 @@ __global__ void __launch_bounds__(128) k_pass1_inv(const ExecDesc* __restrict__ 
     const int col = (it.b << ltc) + c;
     const int step = F1 >> 4;
     const cx<T>* tw = reinterpret_cast<const cx<T>*>(g.tw);
-    cx<T>* slice = lds + c * slice_stride(F1);
     const cx<T>* tw1 = reinterpret_cast<const cx<T>*>(g.tw1);
     cx<T> z[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) z[r] = to_t<T>(Source<Src::InvAsy>::pair(d, 0, m, ((lt + r * step) << lg2) + col));
-    ColTw<T> ct;
-    ct.init(tw, F, col, lt, step);
     for (int k = 0; k < d.nblk; ++k) {
+        // indices and addresses are recomputed per block: z alone stays live
+        const int ltk = opaque(lt), colk = opaque(col);
         const int lo = (int)d.win_lo[k], hi = (int)d.win_hi[k] + 1;
         cx<T> v[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int q = 2 * (((lt + r * step) << lg2) + col);
+            const int q = 2 * (((ltk + r * step) << lg2) + colk);
             const int j0 = q <= G ? q : 2 * G - q, j1 = q + 1 <= G ? q + 1 : 2 * G - q - 1;
             v[r] = {in_range(j0, lo, hi) ? z[r].re : (T)0, in_range(j1, lo, hi) ? z[r].im : (T)0};
         }
-        fft_reg<T>(v, slice, lg1, lt, true, tw1, 2 * F1);
+        fft_reg<T>(v, lds + c * slice_stride(F1), lg1, ltk, true, tw1, 2 * F1);
+        // column twiddles after the transform, so they hold no registers across it
+        ColTw<T> ct;
+        ct.init(tw, F, colk, ltk, step);
         cx<T>* out = reinterpret_cast<cx<T>*>(d.tmp) + (int64_t)(k * d.M + m) * g.L;
-        col_store_any<T>(v, ct, lt, lg1, lg2, col, [&](int i, cx<T> x) { stg(out + i, x); });
+        col_store_any<T>(v, ct, ltk, lg1, lg2, colk, [&](int i, cx<T> x) { stg(out + i, x); });
     }
 }
 
@@ -529,18 +520,20 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
     const int njobs = kMulti ? d.nblk * d.M : 1;
     for (int iter = 0; iter < njobs; ++iter) {
         const int job = kMulti ? (iter % d.nblk) * d.M + iter / d.nblk : 0;
+        // addresses are recomputed per job rather than held across the loop
+        const int ltj = opaque(lt), tidj = opaque(tid);
         const cx<T>* in = reinterpret_cast<const cx<T>*>(d.tmp) + (int64_t)job * L + (int64_t)my_row * L2;
         cx<T> v[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = ldg(in + lt + r * tpr);
+        for (int r = 0; r < 16; ++r) v[r] = ldg(in + ltj + r * tpr);
         cx<T>* slice = buf + rs * sst;
-        fft_reg<T>(v, slice, g.logL2, lt, true, reinterpret_cast<const cx<T>*>(g.tw2), 2 * L2);
+        fft_reg<T>(v, slice, g.logL2, ltj, true, reinterpret_cast<const cx<T>*>(g.tw2), 2 * L2);
 #pragma unroll
-        for (int s = 0; s < 16; ++s) slice[lds_pad(fft_out_index(s, lt, g.logL2))] = v[s];
+        for (int s = 0; s < 16; ++s) slice[lds_pad(fft_out_index(s, ltj, g.logL2))] = v[s];
         __syncthreads();
 #pragma unroll 2
         for (int q = 0; q < ept; ++q) {
-            const int eps = tid + q * nth;
+            const int eps = tidj + q * nth;
             const int lu = eps % TU, k2 = eps / TU;
             const int unit = unit0 + lu;
             const int ra = 2 * lu, rb = 2 * lu + 1;
@@ -564,8 +557,8 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
                 s = unit + L1 * k2;
                 untangle<T>(buf[ra * sst + lds_pad(k2)], buf[rb * sst + lds_pad(L2 - 1 - k2)], ldg(tw + s), xa, xb);
             }
-            acc[(2 * q) * nth + tid] += Target<K>::contrib(d, job, s, xa);
-            acc[(2 * q + 1) * nth + tid] += Target<K>::contrib(d, job, L - s, xb);
+            acc[(2 * q) * nth + tidj] += Target<K>::contrib(d, job, s, xa);
+            acc[(2 * q + 1) * nth + tidj] += Target<K>::contrib(d, job, L - s, xb);
         }
         if (has_half) {
             cx<T> z = buf[lds_pad(L2 / 2)];  // row 0, position L2/2: s = L/2
