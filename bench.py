@@ -270,7 +270,36 @@ def extra_workloads(torch, cjt, inputs, seed):
     log(f"uneven batch of 4096: graph replay p50 {gm:.2f} ms ({coeffs / (gm * 1e-3):.3e} coeff/s), one-shot "
         f"{om:.2f} ms, plans {t_plan:.1f} s")
     batch.destroy()
+    out["jacobi_to_jacobi_256_N16384"] = jacobi_to_jacobi_workload(torch, cjt, inputs, seed)
     return out
+
+
+def jacobi_to_jacobi_workload(torch, cjt, inputs, seed):
+    """256 Jacobi-to-Jacobi transforms at N = 16384, (a, b) -> (c, d) with all
+    four parameters ~ U(-1/2, 1/2) per instance: one batched forward and one
+    batched inverse through the library's Chebyshev buffer.  The accuracy
+    figure is the relative 2-norm error of transforming back to (a, b); parity
+    with the oracle is the tests' job."""
+    count, N = 256, 16384
+    src = inputs.batch_uniform_params(count, N, seed, r=1.0)
+    dst = inputs.batch_uniform_params(count, N, seed + 1000, r=1.0)
+    t0 = time.perf_counter()
+    ps = [cjt.cjt_plan(i.N, i.alpha, i.beta) for i in src]
+    pd = [cjt.cjt_plan(i.N, i.alpha, i.beta) for i in dst]
+    t_plan = time.perf_counter() - t0
+    offs = np.arange(count + 1, dtype=np.int64) * (N + 1)
+    x = torch.as_tensor(np.concatenate([i.coeffs for i in src]), device="cuda")
+    y = torch.empty_like(x)
+    ms, m99 = event_ms(torch, lambda: cjt.cjt_jacobi_to_jacobi_batched(ps, pd, offs, x, y), 10, 2)
+    back = torch.empty_like(x)
+    cjt.cjt_jacobi_to_jacobi_batched(pd, ps, offs, y, back)
+    xr = x.cpu().numpy()
+    err = float(np.linalg.norm(back.cpu().numpy() - xr) / np.linalg.norm(xr))
+    coeffs = count * (N + 1)
+    log(f"Jacobi-to-Jacobi 256 x N=16384: {ms:.2f} ms ({coeffs / (ms * 1e-3):.3e} coeff/s), there-and-back rel-2 "
+        f"{err:.2e}, plans {t_plan:.1f} s")
+    return {"p50_ms": ms, "p99_ms": m99, "coefficients_per_s": coeffs / (ms * 1e-3),
+            "there_and_back_rel_error": err, "plan_s": t_plan}
 
 
 def main():

@@ -136,6 +136,25 @@ cjt_status cjt_forward_batched(const cjt_plan_t* plans, int64_t count, const int
 cjt_status cjt_inverse_batched(const cjt_plan_t* plans, int64_t count, const int64_t* offsets,
                                const double* d_in, double* d_out, void* stream);
 
+/* Jacobi-to-Jacobi transform by composition (Conclusions: the forward
+ * transform followed by the inverse one changes the parameters of an
+ * expansion): d_out = inverse_to(forward_from(d_in)), so that
+ * sum_n d_in[n] P_n^(a,b) = sum_n d_out[n] P_n^(c,d) with (a, b) the
+ * parameters of `from` and (c, d) those of `to`.  Both plans have the same
+ * N and precision flag; d_in and d_out hold N+1 doubles each in device memory
+ * and must not overlap.  The Chebyshev coefficients in between live in a
+ * buffer the library keeps per device and stream (grown on demand, which
+ * synchronizes the stream once).  Errors: CJT_EINVAL for null or overlapping
+ * buffers, differing N or precision; otherwise those of cjt_forward and
+ * cjt_inverse. */
+cjt_status cjt_jacobi_to_jacobi(cjt_plan_t from, cjt_plan_t to, const double* d_in, double* d_out, void* stream);
+
+/* Batched Jacobi-to-Jacobi: transform i uses from[i] and to[i] (host arrays,
+ * from[i] and to[i] of the same N) on the ragged slices given by offsets, as
+ * in cjt_forward_batched; one batched forward and one batched inverse. */
+cjt_status cjt_jacobi_to_jacobi_batched(const cjt_plan_t* from, const cjt_plan_t* to, int64_t count,
+                                        const int64_t* offsets, const double* d_in, double* d_out, void* stream);
+
 /* Persistent batch (Sec. 4: many sets of coefficients, one plan each).
  * cjt_batch_create does all host-side work once: it lays out the launch
  * program for `count` transforms (plans[i], ragged slices given by the host

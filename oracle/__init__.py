@@ -11,6 +11,7 @@ from .oracle import (  # noqa: F401
     build,
     forward,
     inverse,
+    jacobi_to_jacobi,
     point_values,
     point_values_rows,
     jacobi_column,

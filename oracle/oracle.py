@@ -101,6 +101,15 @@ def inverse(cheb, alpha, beta, threads=None, quad=False):
     return out
 
 
+def jacobi_to_jacobi(c, alpha, beta, gamma, delta, threads=None, quad=False):
+    """Coefficients in P_n^(gamma,delta) of the Jacobi series c in P_n^(alpha,beta)
+    (length N+1): the forward transform at (alpha, beta) followed by the inverse
+    at (gamma, delta), the composition named in the paper's conclusions.  The
+    Chebyshev coefficients in between are rounded to FP64, as they are on the
+    GPU path."""
+    return inverse(forward(c, alpha, beta, threads, quad), gamma, delta, threads, quad)
+
+
 def point_values(c, alpha, beta, threads=None, quad=False):
     """p_j = sum_n c_n P_n(cos(pi j/N)), j = 0..N."""
     c = np.ascontiguousarray(c, dtype=np.float64)

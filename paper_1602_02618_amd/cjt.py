@@ -25,6 +25,7 @@ CJT_MAX_BLOCKS = 16
 
 _EXPORTS = (
     "cjt_plan", "cjt_forward", "cjt_inverse", "cjt_forward_batched", "cjt_inverse_batched",
+    "cjt_jacobi_to_jacobi", "cjt_jacobi_to_jacobi_batched",
     "cjt_plan_query", "cjt_plan_describe", "cjt_plan_destroy", "cjt_strerror", "cjt_last_error",
     "cjt_version", "cjt_profile_enable", "cjt_profile_collect",
     "cjt_batch_create", "cjt_batch_execute", "cjt_batch_query", "cjt_batch_destroy",
@@ -176,6 +177,8 @@ def load(path=LIB_PATH):
         lib.cjt_inverse.argtypes = [vp, vp, vp, vp]
         lib.cjt_forward_batched.argtypes = [P(vp), i64, P(i64), vp, vp, vp]
         lib.cjt_inverse_batched.argtypes = [P(vp), i64, P(i64), vp, vp, vp]
+        lib.cjt_jacobi_to_jacobi.argtypes = [vp, vp, vp, vp, vp]
+        lib.cjt_jacobi_to_jacobi_batched.argtypes = [P(vp), P(vp), i64, P(i64), vp, vp, vp]
         lib.cjt_plan_query.argtypes = [vp, P(cjt_plan_info)]
         lib.cjt_plan_describe.argtypes = [i64, dbl, dbl, ci, cu, P(cjt_plan_info)]
         lib.cjt_plan_destroy.argtypes = [vp]
@@ -313,6 +316,22 @@ def cjt_forward_batched(plans, offsets, d_in, d_out, stream=None):
 
 def cjt_inverse_batched(plans, offsets, d_in, d_out, stream=None):
     _batched(load().cjt_inverse_batched, "cjt_inverse_batched", plans, offsets, d_in, d_out, stream)
+
+
+def cjt_jacobi_to_jacobi(src, dst, d_in, d_out, stream=None):
+    _check(load().cjt_jacobi_to_jacobi(src.handle, dst.handle, _ptr(d_in), _ptr(d_out), _stream(stream)),
+           "cjt_jacobi_to_jacobi")
+
+
+def cjt_jacobi_to_jacobi_batched(src, dst, offsets, d_in, d_out, stream=None):
+    n = len(src)
+    a = (ctypes.c_void_p * max(n, 1))(*[p.handle for p in src])
+    b = (ctypes.c_void_p * max(len(dst), 1))(*[p.handle for p in dst])
+    if len(dst) != n:
+        raise ValueError("source and target plan lists differ in length")
+    offs = (ctypes.c_int64 * (n + 1))(*[int(o) for o in offsets])
+    _check(load().cjt_jacobi_to_jacobi_batched(a, b, n, offs, _ptr(d_in), _ptr(d_out), _stream(stream)),
+           "cjt_jacobi_to_jacobi_batched")
 
 
 class Batch:
@@ -535,4 +554,13 @@ def inverse(plan, x, stream=None):
     import torch
     out = torch.empty_like(x)
     cjt_inverse(plan, x, out, stream)
+    return out
+
+
+def jacobi_to_jacobi(src, dst, x, stream=None):
+    """Allocate and return the coefficients in dst's parameters of the
+    expansion with coefficients x (GPU tensor) in src's parameters."""
+    import torch
+    out = torch.empty_like(x)
+    cjt_jacobi_to_jacobi(src, dst, x, out, stream)
     return out

@@ -116,6 +116,8 @@ struct Workspace {
     char* h_meta = nullptr;       // pinned staging of the same
     size_t meta_cap = 0;
     hipEvent_t copied = nullptr;  // staging buffer free once this completes
+    double* mid = nullptr;        // Jacobi-to-Jacobi: Chebyshev coefficients between the two halves
+    size_t mid_cap = 0;           // doubles
     bool pending = false;
 };
 
@@ -450,6 +452,60 @@ cjt_status cjt_inverse_batched(const cjt_plan_t* plans, int64_t count, const int
                                double* d_out, void* stream)
 {
     return batched(true, plans, count, offsets, d_in, d_out, stream);
+}
+
+// Forward with `from`, inverse with `to`, through the stream's buffer of
+// Chebyshev coefficients (total doubles).
+static cjt_status compose(const std::vector<const Plan*>& from, const std::vector<const Plan*>& to,
+                          const std::vector<int64_t>& off, int64_t total, const double* in, double* out,
+                          hipStream_t st)
+{
+    if ((from[0]->flags & CJT_FP32_BULK) != (to[0]->flags & CJT_FP32_BULK))
+        return fail(CJT_EINVAL, "source and target plans must share the precision flag");
+    for (size_t i = 0; i < from.size(); ++i)
+        if (from[i]->N != to[i]->N) return fail(CJT_EINVAL, "source and target plans differ in N");
+    int dev = 0;
+    CJT_HIP_TRY(hipGetDevice(&dev));
+    double* mid = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        Workspace& ws = g_ws[{dev, st}];
+        if ((size_t)total > ws.mid_cap) {
+            CJT_HIP_TRY(hipStreamSynchronize(st));
+            if (ws.mid) CJT_HIP_TRY(hipFree(ws.mid));
+            ws.mid = nullptr;
+            ws.mid_cap = 0;
+            if (hipMalloc((void**)&ws.mid, sizeof(double) * (size_t)total) != hipSuccess)
+                return fail(CJT_ENOMEM, "Chebyshev buffer allocation failed");
+            ws.mid_cap = (size_t)total;
+        }
+        mid = ws.mid;
+    }
+    cjt_status s = execute(false, from, off, in, mid, st);
+    if (s != CJT_OK) return s;
+    return execute(true, to, off, mid, out, st);
+}
+
+cjt_status cjt_jacobi_to_jacobi(cjt_plan_t from, cjt_plan_t to, const double* d_in, double* d_out, void* stream)
+{
+    if (!from || !to || !d_in || !d_out) return fail(CJT_EINVAL, "null argument");
+    if ((const void*)d_in == (const void*)d_out) return fail(CJT_EINVAL, "in-place transforms are not supported");
+    return compose({&from->p}, {&to->p}, {0}, from->p.N + 1, d_in, d_out, (hipStream_t)stream);
+}
+
+cjt_status cjt_jacobi_to_jacobi_batched(const cjt_plan_t* from, const cjt_plan_t* to, int64_t count,
+                                        const int64_t* offsets, const double* d_in, double* d_out, void* stream)
+{
+    if (count < 0 || (count > 0 && (!from || !to || !offsets || !d_in || !d_out)))
+        return fail(CJT_EINVAL, "null argument");
+    if (count == 0) return CJT_OK;
+    if ((const void*)d_in == (const void*)d_out) return fail(CJT_EINVAL, "in-place transforms are not supported");
+    std::vector<const Plan*> vf, vt;
+    std::vector<int64_t> off, off2;
+    cjt_status s = gather(from, count, offsets, &vf, &off);
+    if (s != CJT_OK) return s;
+    if ((s = gather(to, count, offsets, &vt, &off2)) != CJT_OK) return s;
+    return compose(vf, vt, off, offsets[count], d_in, d_out, (hipStream_t)stream);
 }
 
 static void batch_free(cjt_batch_s* b)

@@ -192,3 +192,13 @@ def test_schedule_table_host(lib, tmp_path):
     finally:
         for key in ((65536, 0, 0, 0), (1 << 17, 1, 0, 0), (1 << 18, 0, 1, 0)):
             lib.cjt_tune_set(*key, -1)
+
+
+def test_jacobi_to_jacobi_null_arguments(lib):
+    """Argument checks of the Jacobi-to-Jacobi entry points return before any
+    device work: null plans or buffers are CJT_EINVAL, an empty batch is OK."""
+    raw = lib.load()
+    assert raw.cjt_jacobi_to_jacobi(None, None, None, None, None) == lib.CJT_EINVAL
+    assert raw.cjt_jacobi_to_jacobi_batched(None, None, 1, None, None, None, None) == lib.CJT_EINVAL
+    assert raw.cjt_jacobi_to_jacobi_batched(None, None, -1, None, None, None, None) == lib.CJT_EINVAL
+    assert raw.cjt_jacobi_to_jacobi_batched(None, None, 0, None, None, None, None) == lib.CJT_OK
