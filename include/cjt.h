@@ -59,9 +59,16 @@ enum {
     CJT_FP64 = 0,          /* every step in FP64 */
     CJT_FP32_BULK = 1,     /* the DCT-I/DST-I of the Hahn blocks in FP32 with FP32 accumulation;
                               diagonals, recurrences and boundary DCTs stay FP64 */
-    CJT_BATCH_INVARIANT = 8 /* results of this plan are bitwise the same whatever else shares a
+    CJT_BATCH_INVARIANT = 8, /* results of this plan are bitwise the same whatever else shares a
                               batched call: its recurrence segments are sized from its own
                               degree alone instead of from the whole batch */
+    CJT_SHIFT = 16          /* parameters -1 < alpha, beta <= 5/2: the core runs at the integer
+                              shift (alpha0, beta0) in (-1/2, 1/2]^2 and the coefficients are
+                              carried between the two families by the relation between
+                              neighbouring parameters (Sec. 1.2), O(N) per unit of shift.  The
+                              inverse's error grows like N^s for s unit shifts up (the paper's
+                              remark on large parameters), hence the cap.  Not for servers or
+                              persistent batches */
 };
 
 /* Direction flags of a persistent batch. */
@@ -104,6 +111,8 @@ typedef struct {
     size_t device_bytes;     /* device memory held by the plan */
     int32_t fft_log2_cols_fwd; /* two-pass split of the forward FFTs: log2 of the column length (0: one pass) */
     int32_t fft_log2_cols_inv; /* the same for the inverse's length-2N FFTs */
+    int32_t shift_alpha;     /* CJT_SHIFT: alpha - alpha0 (integer), else 0 */
+    int32_t shift_beta;      /* beta - beta0 */
 } cjt_plan_info;
 
 /* Create a plan for degree 1 <= N <= 2^21 (larger N return CJT_EUNSUPPORTED;

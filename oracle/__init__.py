@@ -11,6 +11,8 @@ from .oracle import (  # noqa: F401
     build,
     forward,
     inverse,
+    inverse_shifted,
+    shift_coefficients,
     jacobi_to_jacobi,
     point_values,
     point_values_rows,

@@ -110,6 +110,86 @@ def jacobi_to_jacobi(c, alpha, beta, gamma, delta, threads=None, quad=False):
     return inverse(forward(c, alpha, beta, threads, quad), gamma, delta, threads, quad)
 
 
+def _split(x):
+    """Integer shift s and base x - s in (-1/2, 1/2]."""
+    import math
+    s = math.ceil(x - 0.5)
+    return s, x - s
+
+
+def shift_coefficients(c, alpha, beta, to_base, dps=40):
+    """Coefficients c of a Jacobi series moved between P^(alpha,beta) and the
+    base family P^(alpha0,beta0), (alpha0, beta0) in (-1/2, 1/2]^2, one unit of
+    parameter at a time by the relation between neighbouring parameters of
+    Sec. 1.2 (for beta) and its image under x -> -x (for alpha), in mpmath at
+    `dps` digits.  With A_n = (n+a+b+1)/(2n+a+b+1), A_0 = 1, and
+    B_n = (n+a)/(2n+a+b+1) (beta) or -(n+b)/(2n+a+b+1) (alpha), coefficients
+    d in P^(a,b) and e in the family raised by one satisfy
+    e_n = A_n d_n + B_{n+1} d_{n+1}; lowering solves this from the top degree
+    down.  to_base: the caller's family to the base (beta first, then alpha);
+    otherwise the reverse."""
+    import mpmath as mp
+    with mp.workdps(dps):
+        v = [mp.mpf(float(x)) for x in c]
+        N = len(v) - 1
+        p, a0 = _split(float(alpha))
+        q, b0 = _split(float(beta))
+        a0, b0 = mp.mpf(a0), mp.mpf(b0)
+
+        def AB(n, a, b, on_a):
+            if n == 0:
+                return mp.mpf(1), mp.mpf(0)
+            den = 2 * n + a + b + 1
+            return (n + a + b + 1) / den, (-(n + b) if on_a else (n + a)) / den
+
+        def up(a, b, on_a):
+            for n in range(N + 1):
+                A = AB(n, a, b, on_a)[0]
+                B1 = AB(n + 1, a, b, on_a)[1]
+                v[n] = A * v[n] + (B1 * v[n + 1] if n < N else 0)
+
+        def down(a, b, on_a):
+            nxt = mp.mpf(0)
+            for n in range(N, -1, -1):
+                A = AB(n, a, b, on_a)[0]
+                B1 = AB(n + 1, a, b, on_a)[1]
+                nxt = (v[n] - B1 * nxt) / A
+                v[n] = nxt
+
+        a1 = a0 + p
+        if to_base:
+            for j in range(q, 0, -1):
+                down(a1, b0 + j - 1, False)
+            for j in range(q, 0):
+                up(a1, b0 + j, False)
+            for i in range(p, 0, -1):
+                down(a0 + i - 1, b0, True)
+            for i in range(p, 0):
+                up(a0 + i, b0, True)
+        else:
+            for i in range(0, p):
+                up(a0 + i, b0, True)
+            for i in range(0, p, -1):
+                down(a0 + i - 1, b0, True)
+            for j in range(0, q):
+                up(a1, b0 + j, False)
+            for j in range(0, q, -1):
+                down(a1, b0 + j - 1, False)
+        return np.array([float(x) for x in v])
+
+
+def inverse_shifted(cheb, alpha, beta, threads=None, quad=False):
+    """Inverse transform for any alpha, beta > -1: the inverse at the base
+    parameters (alpha0, beta0) in (-1/2, 1/2]^2, where its moment recurrence
+    is stable (Sec. 3.1), then the coefficients moved to (alpha, beta) by
+    shift_coefficients.  (The forward transform needs no such route: its
+    definition, evaluation by the three-term recurrence, holds for any
+    alpha, beta > -1.)"""
+    _, a0 = _split(float(alpha))
+    _, b0 = _split(float(beta))
+    return shift_coefficients(inverse(cheb, a0, b0, threads, quad), alpha, beta, to_base=False)
+
+
 def point_values(c, alpha, beta, threads=None, quad=False):
     """p_j = sum_n c_n P_n(cos(pi j/N)), j = 0..N."""
     c = np.ascontiguousarray(c, dtype=np.float64)

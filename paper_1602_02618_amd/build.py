@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcjt_hip.so")
-SOURCES = ["capi.hip", "exec.hip", "plan.hip", "rdft.hip", "rec.hip", "server.hip", "tune.hip"]
+SOURCES = ["capi.hip", "exec.hip", "plan.hip", "rdft.hip", "rec.hip", "server.hip", "shift.hip", "tune.hip"]
 ARCH = os.environ.get("CJT_OFFLOAD_ARCH", "gfx950")
 
 

@@ -19,6 +19,7 @@ CJT_OK, CJT_EINVAL, CJT_EDOMAIN, CJT_ENOMEM, CJT_EDEVICE, CJT_EBUSY, CJT_EUNSUPP
 CJT_FP64 = 0
 CJT_FP32_BULK = 1
 CJT_BATCH_INVARIANT = 8
+CJT_SHIFT = 16
 CJT_DIR_FWD = 2
 CJT_DIR_INV = 4
 CJT_MAX_BLOCKS = 16
@@ -83,6 +84,8 @@ class cjt_plan_info(ctypes.Structure):
         ("device_bytes", ctypes.c_size_t),
         ("fft_log2_cols_fwd", ctypes.c_int32),
         ("fft_log2_cols_inv", ctypes.c_int32),
+        ("shift_alpha", ctypes.c_int32),
+        ("shift_beta", ctypes.c_int32),
     ]
 
 

@@ -118,6 +118,8 @@ struct Workspace {
     hipEvent_t copied = nullptr;  // staging buffer free once this completes
     double* mid = nullptr;        // Jacobi-to-Jacobi: Chebyshev coefficients between the two halves
     size_t mid_cap = 0;           // doubles
+    double* shift = nullptr;      // CJT_SHIFT forward: input moved to the core's parameters
+    size_t shift_cap = 0;         // doubles
     bool pending = false;
 };
 
@@ -184,8 +186,8 @@ cjt_status check_batch(const std::vector<const Plan*>& plans)
     return CJT_OK;
 }
 
-cjt_status execute(bool inverse, const std::vector<const Plan*>& plans, const std::vector<int64_t>& io_off,
-                   const double* in, double* out, hipStream_t st)
+cjt_status execute_core(bool inverse, const std::vector<const Plan*>& plans, const std::vector<int64_t>& io_off,
+                        const double* in, double* out, hipStream_t st)
 {
     if (plans.empty()) return CJT_OK;
     cjt_status s = check_batch(plans);
@@ -213,6 +215,48 @@ cjt_status execute(bool inverse, const std::vector<const Plan*>& plans, const st
                        ws.join, in, out);
 }
 
+// The transform with plans that shift their parameters (CJT_SHIFT): the
+// forward moves the input's coefficients to the core's parameters in a
+// per-stream buffer first; the inverse moves the core's output to the
+// caller's parameters in place afterwards.  Instances are contiguous from
+// io_off[0] (offsets of the batched calls).
+cjt_status execute(bool inverse, const std::vector<const Plan*>& plans, const std::vector<int64_t>& io_off,
+                   const double* in, double* out, hipStream_t st)
+{
+    bool any = false;
+    for (const Plan* P : plans) any = any || P->sh_a != 0 || P->sh_b != 0;
+    if (!any) return execute_core(inverse, plans, io_off, in, out, st);
+    cjt_status s = CJT_OK;
+    if (inverse) {
+        if ((s = execute_core(true, plans, io_off, in, out, st)) != CJT_OK) return s;
+        for (size_t i = 0; i < plans.size(); ++i)
+            if ((s = apply_shift(*plans[i], out + io_off[i], false, st)) != CJT_OK) return s;
+        return CJT_OK;
+    }
+    const int64_t lo = io_off.front(), hi = io_off.back() + plans.back()->N + 1;
+    int dev = 0;
+    CJT_HIP_TRY(hipGetDevice(&dev));
+    double* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        Workspace& ws = g_ws[{dev, st}];
+        if ((size_t)hi > ws.shift_cap) {
+            CJT_HIP_TRY(hipStreamSynchronize(st));
+            if (ws.shift) CJT_HIP_TRY(hipFree(ws.shift));
+            ws.shift = nullptr;
+            ws.shift_cap = 0;
+            if (hipMalloc((void**)&ws.shift, sizeof(double) * (size_t)hi) != hipSuccess)
+                return fail(CJT_ENOMEM, "shift buffer allocation failed");
+            ws.shift_cap = (size_t)hi;
+        }
+        base = ws.shift;
+    }
+    CJT_HIP_TRY(hipMemcpyAsync(base + lo, in + lo, sizeof(double) * (size_t)(hi - lo), hipMemcpyDeviceToDevice, st));
+    for (size_t i = 0; i < plans.size(); ++i)
+        if ((s = apply_shift(*plans[i], base + io_off[i], true, st)) != CJT_OK) return s;
+    return execute_core(false, plans, io_off, base, out, st);
+}
+
 void fill_part_info(const Part& p, cjt_partition_info* o)
 {
     memset(o, 0, sizeof(*o));
@@ -236,8 +280,10 @@ void describe(const Plan& P, cjt_plan_info* out)
 {
     memset(out, 0, sizeof(*out));
     out->N = P.N;
-    out->alpha = P.alpha;
-    out->beta = P.beta;
+    out->alpha = P.alpha + P.sh_a;  // the caller's parameters
+    out->beta = P.beta + P.sh_b;
+    out->shift_alpha = P.sh_a;
+    out->shift_beta = P.sh_b;
     out->M = std::max(P.fwd.M, P.inv.M);
     out->flags = P.flags;
     out->eps = 2.220446049250313080847263336181640625e-16;
@@ -261,15 +307,25 @@ cjt_status check_args(int64_t N, double alpha, double beta, int M, unsigned flag
 {
     if (N < 1) return fail(CJT_EINVAL, "N must be >= 1");
     if (N > kMaxN) return fail(CJT_EUNSUPPORTED, "N above 2^21 is not supported");
-    if (!isfinite(alpha) || !isfinite(beta) || !(alpha > -0.5 && alpha <= 0.5) || !(beta > -0.5 && beta <= 0.5))
+    if (flags & CJT_SHIFT) {
+        if (!isfinite(alpha) || !isfinite(beta) || !(alpha > -1.0 && alpha <= kMaxShiftParam) ||
+            !(beta > -1.0 && beta <= kMaxShiftParam))
+            return fail(CJT_EDOMAIN, "with CJT_SHIFT, alpha and beta must lie in (-1, 5/2]");
+    } else if (!isfinite(alpha) || !isfinite(beta) || !(alpha > -0.5 && alpha <= 0.5) ||
+               !(beta > -0.5 && beta <= 0.5)) {
         return fail(CJT_EDOMAIN, "alpha and beta must lie in (-1/2, 1/2]");
+    }
     if (M != 0 && (M < 2 || M > kMaxM)) return fail(CJT_EDOMAIN, "M must be 0 (auto) or in [2, 30]");
-    if (flags & ~(unsigned)(CJT_FP32_BULK | CJT_BATCH_INVARIANT)) return fail(CJT_EINVAL, "unknown flag");
+    if (flags & ~(unsigned)(CJT_FP32_BULK | CJT_BATCH_INVARIANT | CJT_SHIFT)) return fail(CJT_EINVAL, "unknown flag");
     return CJT_OK;
 }
 
 void plan_host(Plan* P, int64_t N, double alpha, double beta, int M, unsigned flags)
 {
+    if (flags & CJT_SHIFT) {  // the core at the base parameters
+        shift_split(alpha, &P->sh_a, &alpha);
+        shift_split(beta, &P->sh_b, &beta);
+    }
     P->N = N;
     P->alpha = alpha;
     P->beta = beta;
@@ -530,6 +586,9 @@ cjt_status cjt_batch_create(cjt_batch_t* out, const cjt_plan_t* plans, int64_t c
     cjt_status s = gather(plans, count, offsets, &v, &off);
     if (s != CJT_OK) return s;
     if ((s = check_batch(v)) != CJT_OK) return s;
+    for (const Plan* P : v)
+        if (P->sh_a != 0 || P->sh_b != 0)
+            return fail(CJT_EUNSUPPORTED, "persistent batches take plans without parameter shifts");
     hipStream_t st = (hipStream_t)stream;
     cjt_batch_s* b = new (std::nothrow) cjt_batch_s;
     if (!b) return fail(CJT_ENOMEM, "host allocation failed");

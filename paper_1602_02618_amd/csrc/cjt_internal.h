@@ -182,6 +182,7 @@ constexpr int64_t kSingleMax = 4096;
 // Largest degree: the inverse's length-2N transform must fit the two-pass
 // engine (power-of-two lengths up to 2^22, chirp-z convolutions up to 2^24).
 constexpr int64_t kMaxN = (int64_t)1 << 21;
+constexpr double kMaxShiftParam = 2.5;  // CJT_SHIFT: at most 2 unit shifts up per parameter
 
 // Bytes of intermediate storage one job of the FFT engine needs for length L.
 size_t fft_job_bytes(int64_t L, bool fp32);

@@ -52,6 +52,9 @@ struct Plan {
     // log2 of the column length of the two-pass FFTs of the forward (N) and
     // inverse (2N) grids, from the schedule table at planning time (-1: default)
     int lg1_f = -1, lg1_i = -1;
+    // integer parameter shifts (Sec. 1.2): the caller's parameters are
+    // (alpha + sh_a, beta + sh_b); alpha, beta above are the core's, in (-1/2, 1/2]
+    int sh_a = 0, sh_b = 0;
 };
 
 constexpr int kRecWidthFwd = 64 * 4;    // points per forward recurrence task (4 per lane)
@@ -60,6 +63,11 @@ constexpr int kRecWidthInv = 64 * 4;    // points per inverse task (4 per lane)
 void compute_partition(int64_t G, int64_t cap, double a, double b, int M, Part* P);
 void choose_partitions(int64_t N, double a, double b, int M, Part* f, Part* inv);
 void build_tasks(const Part& P, int width, std::vector<RecTask>* out, int64_t* part_total);
+// Integer shift s and base x - s in (-1/2, 1/2] of a parameter x > -1.
+void shift_split(double x, int* shift, double* base);
+// Moves the N+1 coefficients v between the caller's parameters and the
+// core's (to_base) or back, on st; no-op for plans without shifts.
+cjt_status apply_shift(const Plan& P, double* v, bool to_base, hipStream_t st);
 // Argument checks shared by every entry point that creates plans.
 cjt_status check_args(int64_t N, double alpha, double beta, int M, unsigned flags);
 // Host half of plan creation: partitions, recurrence tasks, arena layout.

@@ -202,3 +202,21 @@ def test_jacobi_to_jacobi_null_arguments(lib):
     assert raw.cjt_jacobi_to_jacobi_batched(None, None, 1, None, None, None, None) == lib.CJT_EINVAL
     assert raw.cjt_jacobi_to_jacobi_batched(None, None, -1, None, None, None, None) == lib.CJT_EINVAL
     assert raw.cjt_jacobi_to_jacobi_batched(None, None, 0, None, None, None, None) == lib.CJT_OK
+
+
+@pytest.mark.parametrize("a,b,sa,sb", [(1.3, 0.1, 1, 0), (-0.7, 2.4, -1, 2), (0.5, -0.5, 0, -1), (2.5, -0.95, 2, -1)])
+def test_shift_split_on_the_host(lib, a, b, sa, sb):
+    """CJT_SHIFT plans (Sec. 1.2 shifts): the core runs at (a - sa, b - sb) in
+    (-1/2, 1/2]^2; the plan reports the caller's parameters and the shifts."""
+    info = lib.cjt_plan_describe(1024, a, b, 0, lib.CJT_SHIFT)
+    assert (info.shift_alpha, info.shift_beta) == (sa, sb)
+    assert abs(info.alpha - a) < 1e-15 and abs(info.beta - b) < 1e-15
+    base = lib.cjt_plan_describe(1024, a - sa, b - sb, 0)
+    assert info.fwd.rec_entries == base.fwd.rec_entries and info.inv.nblocks == base.inv.nblocks
+
+
+@pytest.mark.parametrize("a,b", [(2.6, 0.1), (-1.0, 0.0), (0.0, float("nan"))])
+def test_shift_domain(lib, a, b):
+    with pytest.raises(lib.CJTError) as e:
+        lib.cjt_plan_describe(1024, a, b, 0, lib.CJT_SHIFT)
+    assert e.value.status == lib.CJT_EDOMAIN
