@@ -271,7 +271,35 @@ def extra_workloads(torch, cjt, inputs, seed):
         f"{om:.2f} ms, plans {t_plan:.1f} s")
     batch.destroy()
     out["jacobi_to_jacobi_256_N16384"] = jacobi_to_jacobi_workload(torch, cjt, inputs, seed)
+    out["shifted_N65536"] = shifted_workload(torch, cjt, seed)
     return out
+
+
+def shifted_workload(torch, cjt, seed):
+    """One transform at N = 65536 with (alpha, beta) = (1.5, -0.7), outside
+    (-1/2, 1/2]^2 (CJT_SHIFT: core at (0.5, 0.3), one unit of shift in each
+    parameter), against the same N at the base parameters: the cost of the
+    O(N) coefficient moves."""
+    N = 65536
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal(N + 1) / (np.arange(N + 1) + 1.0)
+    ps = cjt.cjt_plan(N, 1.5, -0.7, 0, cjt.CJT_SHIFT)
+    pb = cjt.cjt_plan(N, 0.5, 0.3)
+    x = torch.as_tensor(c, device="cuda")
+    f = torch.empty_like(x)
+    g = torch.empty_like(x)
+    r = {}
+    for name, p in (("shifted", ps), ("base", pb)):
+        fm, _ = event_ms(torch, lambda: cjt.cjt_forward(p, x, f), 20, 3)
+        im, _ = event_ms(torch, lambda: cjt.cjt_inverse(p, f, g), 20, 3)
+        r[name] = {"forward_ms": fm, "inverse_ms": im}
+    cjt.cjt_forward(ps, x, f)
+    cjt.cjt_inverse(ps, f, g)
+    r["shifted"]["round_trip_rel_error"] = float(np.linalg.norm(g.cpu().numpy() - c) / np.linalg.norm(c))
+    log(f"shifted N=65536 (1.5,-0.7): forward {r['shifted']['forward_ms']:.3f} ms, inverse "
+        f"{r['shifted']['inverse_ms']:.3f} ms; base (0.5,0.3): forward {r['base']['forward_ms']:.3f} ms, inverse "
+        f"{r['base']['inverse_ms']:.3f} ms; round trip {r['shifted']['round_trip_rel_error']:.2e}")
+    return r
 
 
 def jacobi_to_jacobi_workload(torch, cjt, inputs, seed):
