@@ -222,7 +222,8 @@ enum class Kind : int32_t {
     FftSingle,       // whole power-of-two transform in one workgroup, all jobs of an instance
     FftPass1,        // column pass of a two-pass transform, one (job, column tile)
     FftPass1Inv,     // inverse Hahn blocks: column pass of every block of one (term, column tile)
-    FftPass2,        // row pass + untangling + sink, all jobs of an instance, one row tile
+    FftPass2,        // row pass + untangling + sink, all jobs (or one job) of an instance, one row tile
+    JobRowReduce,    // sum of the per-job row-pass parts in job order, then the sink
     BsSingle,        // chirp-z transform in one workgroup
     BsCol1,     // chirp-z, two passes: column pass of the first transform
     BsRowConv,  // row FFT, kernel product, inverse row FFT, in place

@@ -51,6 +51,16 @@ namespace cjt {
 
 __device__ __forceinline__ bool in_range(int n, int lo, int hi) { return (unsigned)(n - lo) < (unsigned)(hi - lo); }
 
+// a += v as its own rounding: v passes through an empty register barrier, so
+// no product inside v is fused with this add.  Sums over the jobs of an
+// instance therefore round the same way whether one workgroup adds them in
+// turn or a reduce adds per-job parts in the same order.
+__device__ __forceinline__ void accum(double& a, double v)
+{
+    asm volatile("" : "+v"(v));
+    a += v;
+}
+
 template <Src S>
 struct Source;
 
@@ -402,8 +412,8 @@ __global__ void __launch_bounds__(256) k_single(const ExecDesc* __restrict__ des
             if (s >= nel) break;
             cx<double> xa, xb;
             untangle_at<T>([&](int i) { return buf[lds_pad(i)]; }, L, s, ldg(tw + s), xa, xb);
-            acc[(2 * q) * nth + tid] += Target<K>::contrib(d, job, s, xa);
-            if (2 * s != L) acc[(2 * q + 1) * nth + tid] += Target<K>::contrib(d, job, L - s, xb);
+            accum(acc[(2 * q) * nth + tid], Target<K>::contrib(d, job, s, xa));
+            if (2 * s != L) accum(acc[(2 * q + 1) * nth + tid], Target<K>::contrib(d, job, L - s, xb));
         }
         __syncthreads();
     }
@@ -484,11 +494,27 @@ __global__ void __launch_bounds__(128) k_pass1_inv(const ExecDesc* __restrict__ 
     }
 }
 
-// Row pass, item (desc, unit tile): TU units per workgroup; unit u holds rows
-// u and L1-u (unit 0 holds rows 0 and L1/2).  Element (u, k2) pairs Z at row
-// u, position k2 with Z at row L1-u, position L2-1-k2, which are Z_s and
-// Z_{L-s} for s = u + L1 k2.  The L2-point FFTs run in registers; their
-// outputs go through LDS once so each thread can fetch both members of its pairs.
+// Per-job parts of the row pass (job-parallel mode): after the two-pass
+// intermediates of every job, L + 1 doubles per job in iteration order.
+template <typename T>
+__device__ __forceinline__ double* row_parts(const ExecDesc& d, int L)
+{
+    return reinterpret_cast<double*>(reinterpret_cast<cx<T>*>(d.tmp) + (int64_t)d.nblk * d.M * L);
+}
+
+// Row pass, item (desc, iteration, unit tile, one_job): TU units per
+// workgroup; unit u holds rows u and L1-u (unit 0 holds rows 0 and L1/2).
+// Element (u, k2) pairs Z at row u, position k2 with Z at row L1-u, position
+// L2-1-k2, which are Z_s and Z_{L-s} for s = u + L1 k2.  The L2-point FFTs run
+// in registers; their outputs go through LDS once so each thread can fetch
+// both members of its pairs.
+//
+// Normally a workgroup sums every job of its rows.  In job-parallel mode
+// (one_job, for calls with few instances, where the row tiles alone cannot
+// fill the GPU) it takes only iteration `iteration` and stores that job's
+// part; k_job_row_reduce then adds the parts in iteration order, which is
+// the order and association of the fused sum, so both modes give bitwise the
+// same results.
 template <typename T, Sink K, bool kMulti>
 __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ descs, const Item* __restrict__ items,
                                                size_t acc_off)
@@ -518,7 +544,9 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
     // jobs in the order (m, k), k fastest, so that the diagonals of term m are
     // re-read from L2 for every block
     const int njobs = kMulti ? d.nblk * d.M : 1;
-    for (int iter = 0; iter < njobs; ++iter) {
+    const bool one_job = kMulti && it.c != 0;
+    const int iter0 = one_job ? it.a : 0, iter1 = one_job ? it.a + 1 : njobs;
+    for (int iter = iter0; iter < iter1; ++iter) {
         const int job = kMulti ? (iter % d.nblk) * d.M + iter / d.nblk : 0;
         // addresses are recomputed per job rather than held across the loop
         const int ltj = opaque(lt), tidj = opaque(tid);
@@ -557,15 +585,20 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
                 s = unit + L1 * k2;
                 untangle<T>(buf[ra * sst + lds_pad(k2)], buf[rb * sst + lds_pad(L2 - 1 - k2)], ldg(tw + s), xa, xb);
             }
-            acc[(2 * q) * nth + tidj] += Target<K>::contrib(d, job, s, xa);
-            acc[(2 * q + 1) * nth + tidj] += Target<K>::contrib(d, job, L - s, xb);
+            accum(acc[(2 * q) * nth + tidj], Target<K>::contrib(d, job, s, xa));
+            accum(acc[(2 * q + 1) * nth + tidj], Target<K>::contrib(d, job, L - s, xb));
         }
         if (has_half) {
             cx<T> z = buf[lds_pad(L2 / 2)];  // row 0, position L2/2: s = L/2
-            acc[(2 * ept) * nth + tid] += Target<K>::contrib(d, job, L / 2, cx<double>{(double)z.re, (double)z.im});
+            accum(acc[(2 * ept) * nth + tid], Target<K>::contrib(d, job, L / 2, cx<double>{(double)z.re, (double)z.im}));
         }
         __syncthreads();
     }
+    double* part = one_job ? row_parts<T>(d, L) + (int64_t)it.a * (L + 1) : nullptr;
+    auto put = [&](int s, double v) {
+        if (part) stg(part + s, v);
+        else Target<K>::finish(d, s, v);
+    };
 #pragma unroll
     for (int q = 0; q < ept; ++q) {
         const int eps = tid + q * nth;
@@ -579,10 +612,28 @@ __global__ void __launch_bounds__(256) k_pass2(const ExecDesc* __restrict__ desc
         } else {
             s = unit + L1 * k2;
         }
-        Target<K>::finish(d, s, acc[(2 * q) * nth + tid]);
-        Target<K>::finish(d, L - s, acc[(2 * q + 1) * nth + tid]);
+        put(s, acc[(2 * q) * nth + tid]);
+        put(L - s, acc[(2 * q + 1) * nth + tid]);
     }
-    if (has_half) Target<K>::finish(d, L / 2, acc[(2 * ept) * nth + tid]);
+    if (has_half) put(L / 2, acc[(2 * ept) * nth + tid]);
+}
+
+// item (desc, 0, tile of 256 outputs): the row pass's per-job parts added in
+// iteration order (terms m outer, blocks k inner), then the sink
+template <typename T, Sink K>
+__global__ void __launch_bounds__(256) k_job_row_reduce(const ExecDesc* __restrict__ descs,
+                                                        const Item* __restrict__ items)
+{
+    const Item it = items[blockIdx.x];
+    const ExecDesc& d = descs[it.desc];
+    const int L = (int)geom_of<T>(d).L;
+    const int s = it.b * blockDim.x + threadIdx.x;
+    if (s > L) return;
+    const double* part = row_parts<T>(d, L);
+    const int njobs = d.nblk * d.M;
+    double acc = 0.0;
+    for (int iter = 0; iter < njobs; ++iter) accum(acc, ldg(part + (int64_t)iter * (L + 1) + s));
+    Target<K>::finish(d, s, acc);
 }
 
 // ------------------------------------------------------------------ chirp-z (any L)
@@ -752,8 +803,8 @@ __global__ void __launch_bounds__(256) k_bs_untangle(const ExecDesc* __restrict_
         const cx<T>* Z = reinterpret_cast<const cx<T>*>(d.tmp) + (int64_t)job * 2 * P + P;
         cx<double> xa, xb;
         untangle_at<T>([&](int i) { return ldg(Z + i); }, L, s, ldg(utw + s), xa, xb);
-        a0 += Target<K>::contrib(d, job, s, xa);
-        if (2 * s != L) a1 += Target<K>::contrib(d, job, L - s, xb);
+        accum(a0, Target<K>::contrib(d, job, s, xa));
+        if (2 * s != L) accum(a1, Target<K>::contrib(d, job, L - s, xb));
     }
     Target<K>::finish(d, s, a0);
     if (2 * s != L) Target<K>::finish(d, L - s, a1);
@@ -797,8 +848,8 @@ __global__ void __launch_bounds__(256) k_bs_single(const ExecDesc* __restrict__ 
             if (sx >= nel) break;
             cx<double> xa, xb;
             untangle_at<T>([&](int i) { return buf[lds_pad(i)]; }, L, sx, ldg(utw + sx), xa, xb);
-            acc[(2 * q) * nth + tid] += Target<K>::contrib(d, job, sx, xa);
-            if (2 * sx != L) acc[(2 * q + 1) * nth + tid] += Target<K>::contrib(d, job, L - sx, xb);
+            accum(acc[(2 * q) * nth + tid], Target<K>::contrib(d, job, sx, xa));
+            if (2 * sx != L) accum(acc[(2 * q + 1) * nth + tid], Target<K>::contrib(d, job, L - sx, xb));
         }
         __syncthreads();
     }
@@ -897,7 +948,7 @@ __global__ void __launch_bounds__(256) k_job_reduce(const ExecDesc* __restrict__
     double acc = 0.0;
     for (int iter = 0; iter < njobs; ++iter) {
         const int job = (iter % d.nblk) * d.M + iter / d.nblk;
-        acc += ldg(reinterpret_cast<const double*>(d.tmp) + (int64_t)job * (L + 1) + s);
+        accum(acc, ldg(reinterpret_cast<const double*>(d.tmp) + (int64_t)job * (L + 1) + s));
     }
     Target<K>::finish(d, s, acc);
 }
@@ -964,6 +1015,9 @@ cjt_status run(const Launch& L, const ExecDesc* dd, const Item* it, hipStream_t 
         if constexpr (S == Src::InvAsy) return go(k_pass1_inv<T>, L, s, dd, it);
         return fail(CJT_EINVAL, "multi-block column pass is for the inverse Hahn blocks");
     case Kind::FftPass2: return go(k_pass2<T, K, kMulti>, L, s, dd, it, L.acc_off);
+    case Kind::JobRowReduce:
+        if constexpr (kMulti) return go(k_job_row_reduce<T, K>, L, s, dd, it);
+        return fail(CJT_EINVAL, "per-job row parts are for the Hahn blocks");
     case Kind::BsSingle: return go(k_bs_single<T, S, K>, L, s, dd, it, L.acc_off);
     case Kind::BsCol1: return go(k_bs_col1<T, S>, L, s, dd, it);
     case Kind::BsRowConv: return go(k_bs_rowconv<T>, L, s, dd, it);
@@ -997,6 +1051,14 @@ cjt_status launch_fft(const Launch& L, const ExecDesc* dd, const Item* it, hipSt
 static bool job_mode(const FftGeom& g, int64_t jobs, bool job_parallel)
 {
     return job_parallel && jobs > 1 && g.single;
+}
+
+// The row pass of a two-pass power-of-two transform takes one job per
+// workgroup (and a reduce) in calls with few instances; same predicate for
+// add_fft and fft_tmp_bytes.
+static bool row_job_mode(const FftGeom& g, int64_t jobs, bool job_parallel)
+{
+    return job_parallel && jobs > 1 && !g.single && !g.bluestein;
 }
 
 // Job of iteration `it` in the order terms m outer, blocks k inner.
@@ -1072,10 +1134,16 @@ cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sin
             b1.flops += 0.5 * fl;
             b1.bytes += 0.5 * by;
             Bucket& b2 = bucket(Kind::FftPass2, nth2, name_rows);
-            for (int t = 0; t < (g.L1 / 2) / TU; ++t) b2.items.push_back(Item{i, 0, t, 0});
+            const bool one_job = multi && row_job_mode(g, jobs, job_parallel);
+            for (int q = 0; q < (one_job ? jobs : 1); ++q)
+                for (int t = 0; t < (g.L1 / 2) / TU; ++t) b2.items.push_back(Item{i, q, t, one_job ? 1 : 0});
             b2.acc = std::max(b2.acc, a256((size_t)2 * TU * slice_stride(g.L2) * esz));
             b2.flops += 0.5 * fl;
             b2.bytes += 0.5 * by;
+            if (one_job) {
+                Bucket& br = bucket(Kind::JobRowReduce, 256, name_rows);
+                for (int64_t t = 0; t < (g.L + 1 + 255) / 256; ++t) br.items.push_back(Item{i, 0, (int32_t)t, 0});
+            }
         } else if (g.single) {
             const int nth = clamp_nth(g.P);
             if ((g.L / 2 + 1 + nth - 1) / nth > kSlots / 2) return fail(CJT_EUNSUPPORTED, "chirp-z length");
@@ -1132,8 +1200,8 @@ cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sin
     };
     // launch order: single-workgroup kinds, then the two-pass chains in dependency order
     const Kind order[] = {Kind::FftSingle, Kind::BsSingle, Kind::FftJobs, Kind::BsJobs,  Kind::JobReduce,
-                          Kind::FftPass1,  Kind::FftPass1Inv, Kind::FftPass2, Kind::BsCol1, Kind::BsRowConv,
-                          Kind::BsCol2Inv, Kind::BsUntangle};
+                          Kind::FftPass1,  Kind::FftPass1Inv, Kind::FftPass2, Kind::JobRowReduce, Kind::BsCol1,
+                          Kind::BsRowConv, Kind::BsCol2Inv, Kind::BsUntangle};
     for (Kind k : order) {
         for (auto& b : bk) {
             if (b.kind != k || b.items.empty()) continue;
@@ -1346,7 +1414,8 @@ size_t fft_tmp_bytes(const FftGeom& g, int64_t jobs, bool fp32, bool job_paralle
 {
     if (jobs <= 0) return 0;
     if (job_mode(g, jobs, job_parallel)) return sizeof(double) * (size_t)jobs * (size_t)(g.L + 1);
-    return (size_t)jobs * fft_job_bytes(g.L, fp32);
+    const size_t parts = row_job_mode(g, jobs, job_parallel) ? sizeof(double) * (size_t)jobs * (size_t)(g.L + 1) : 0;
+    return (size_t)jobs * fft_job_bytes(g.L, fp32) + parts;
 }
 
 size_t fft_job_bytes(int64_t L, bool fp32)

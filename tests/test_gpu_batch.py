@@ -129,3 +129,26 @@ def test_batch_errors(lib):
     with pytest.raises(lib.CJTError) as e:
         lib.cjt_batch_execute(b, x, x)
     assert e.value.status == lib.CJT_EINVAL
+
+
+def test_job_parallel_and_fused_agree(lib):
+    """Calls of at most 64 instances spread each instance's Hahn jobs over
+    workgroups (per-job parts added by a reduce in job order); larger calls add
+    the jobs inside one workgroup.  Both round the same way: a call of 70
+    instances equals each instance run alone, bitwise, in both directions
+    (batch-invariant plans; power-of-two two-pass, single-workgroup and chirp-z
+    lengths)."""
+    import torch
+    rng = np.random.default_rng(24)
+    Ns = [8192, 1000, 5000, 16384, 300] + list(rng.integers(64, 3000, 65))
+    plans = [lib.cjt_plan(int(N), *rng.uniform(-0.5, 0.5, 2), 0, lib.CJT_BATCH_INVARIANT) for N in Ns]
+    cs = [rng.standard_normal(int(N) + 1) / (np.arange(int(N) + 1) + 1.0) for N in Ns]
+    offs = np.concatenate([[0], np.cumsum([int(N) + 1 for N in Ns])]).astype(np.int64)
+    x = torch.as_tensor(np.concatenate(cs), device="cuda")
+    for fn, single in ((lib.cjt_forward_batched, lib.forward), (lib.cjt_inverse_batched, lib.inverse)):
+        y = torch.empty_like(x)
+        fn(plans, offs, x, y)
+        yb = y.cpu().numpy()
+        for i in range(5):
+            ys = single(plans[i], torch.as_tensor(cs[i], device="cuda")).cpu().numpy()
+            assert np.array_equal(yb[offs[i]:offs[i + 1]], ys), (fn.__name__, i, Ns[i])
