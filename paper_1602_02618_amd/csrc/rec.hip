@@ -268,19 +268,32 @@ __global__ void __launch_bounds__(64) k_rec_fwd(const ExecDesc* __restrict__ des
                     }
             }
         } else {
+            // degree 0 ends the modified recurrence without the u update; it
+            // is taken after the loop so the loop body carries no such test
+            const int stop = b0 == 0 ? 1 : 0;
 #pragma unroll 4
-            for (int t = top; t >= 0; --t) {
+            for (int t = top; t >= stop; --t) {
                 const d4 q4 = St.co[t];
                 const double cn = St.c[t];
-                const bool last = (b0 + t) == 0;
 #pragma unroll
                 for (int ch = 0; ch < NC; ++ch)
 #pragma unroll
                     for (int q = 0; q < kPPT; ++q) {
                         const double w = fma(xh[q], s1[ch][q], xl[q] * s1[ch][q]);
                         const double Dn = fma(q4.x, w, fma(q4.y, s2[ch][q], ch == 0 ? cn : 0.0));
-                        if (!last) s1[ch][q] = fma(s1[ch][q], q4.z, Dn);
+                        s1[ch][q] = fma(s1[ch][q], q4.z, Dn);
                         s2[ch][q] = Dn;
+                    }
+            }
+            if (b0 == 0) {
+                const d4 q4 = St.co[0];
+                const double cn = St.c[0];
+#pragma unroll
+                for (int ch = 0; ch < NC; ++ch)
+#pragma unroll
+                    for (int q = 0; q < kPPT; ++q) {
+                        const double w = fma(xh[q], s1[ch][q], xl[q] * s1[ch][q]);
+                        s2[ch][q] = fma(q4.x, w, fma(q4.y, s2[ch][q], ch == 0 ? cn : 0.0));
                     }
             }
         }
