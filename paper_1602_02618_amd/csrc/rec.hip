@@ -416,16 +416,23 @@ __global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ des
         const int bend = min(kBlk, hi - b0);
         for (int c0 = 0; c0 < bend; c0 += kChunk) {
             const int nend = min(kChunk, bend - c0);
-#pragma unroll 4
-            for (int t = 0; t < nend; ++t) {
+            // this lane's points summed at each degree (the first point starts
+            // the sum), for the reduction below
+            auto put = [&](int t) {
                 if (!kMaps) {
-                    double v = 0.0;
+                    double v = pv[0][0];
 #pragma unroll
-                    for (int q = 0; q < kPPT; ++q) v += pv[0][q];
+                    for (int q = 1; q < kPPT; ++q) v += pv[0][q];
                     red[t][lane] = v;
                 }
-                const d4 cf = St.co[c0 + t];
-                if (mode == 0) {
+            };
+            // one loop per form (the form is fixed for the task), so the
+            // unrolled body carries no branch
+            if (mode == 0) {
+#pragma unroll 4
+                for (int t = 0; t < nend; ++t) {
+                    put(t);
+                    const d4 cf = St.co[c0 + t];
 #pragma unroll
                     for (int ch = 0; ch < NC; ++ch)
 #pragma unroll
@@ -435,7 +442,12 @@ __global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ des
                             ev[ch][q] = pv[ch][q];
                             pv[ch][q] = p1;
                         }
-                } else {
+                }
+            } else {
+#pragma unroll 4
+                for (int t = 0; t < nend; ++t) {
+                    put(t);
+                    const d4 cf = St.co[c0 + t];
 #pragma unroll
                     for (int ch = 0; ch < NC; ++ch)
 #pragma unroll
@@ -450,9 +462,9 @@ __global__ void __launch_bounds__(64) k_rec_inv(const ExecDesc* __restrict__ des
             if (!kMaps) {
                 __syncthreads();
                 if (dd < nend) {
-                    double sum = 0.0;
+                    double sum = red[dd][qq * 16];
 #pragma unroll
-                    for (int l = 0; l < 16; ++l) sum += red[dd][qq * 16 + l];
+                    for (int l = 1; l < 16; ++l) sum += red[dd][qq * 16 + l];
                     sum += __shfl_xor(sum, 1);
                     sum += __shfl_xor(sum, 2);
                     if (qq == 0) stg(part + b0 + c0 + dd, sum);
