@@ -1054,11 +1054,12 @@ static bool job_mode(const FftGeom& g, int64_t jobs, bool job_parallel)
 }
 
 // The row pass of a two-pass power-of-two transform takes one job per
-// workgroup (and a reduce) in calls with few instances; same predicate for
-// add_fft and fft_tmp_bytes.
+// workgroup (and a reduce) in calls with few instances, for lengths whose
+// row tiles alone (L / 2048 per instance) cannot fill the GPU; same
+// predicate for add_fft and fft_tmp_bytes.
 static bool row_job_mode(const FftGeom& g, int64_t jobs, bool job_parallel)
 {
-    return job_parallel && jobs > 1 && !g.single && !g.bluestein;
+    return job_parallel && jobs > 1 && !g.single && !g.bluestein && g.L < ((int64_t)1 << 19);
 }
 
 // Job of iteration `it` in the order terms m outer, blocks k inner.
