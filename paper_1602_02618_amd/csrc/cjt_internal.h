@@ -221,7 +221,7 @@ enum class Kind : int32_t {
     Patch,           // in/out pointers of every descriptor from the call's base pointers
     FftSingle,       // whole power-of-two transform in one workgroup, all jobs of an instance
     FftPass1,        // column pass of a two-pass transform, one (job, column tile)
-    FftPass1Inv,     // inverse Hahn blocks: column pass of every block of one (term, column tile)
+    FftPass1Terms,   // Hahn blocks: column pass of every block of one (term, column tile)
     FftPass2,        // row pass + untangling + sink, all jobs (or one job) of an instance, one row tile
     JobRowReduce,    // sum of the per-job row-pass parts in job order, then the sink
     BsSingle,        // chirp-z transform in one workgroup

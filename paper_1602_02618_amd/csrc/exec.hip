@@ -224,7 +224,7 @@ cjt_status build_program(const std::vector<const Plan*>& plans, const std::vecto
     // is an error here rather than a null pointer on the device
     for (const Launch& L : pr.launches) {
         switch (L.kind) {
-        case Kind::FftPass1: case Kind::FftPass1Inv: case Kind::FftPass2: case Kind::JobRowReduce: case Kind::BsCol1: case Kind::BsRowConv:
+        case Kind::FftPass1: case Kind::FftPass1Terms: case Kind::FftPass2: case Kind::JobRowReduce: case Kind::BsCol1: case Kind::BsRowConv:
         case Kind::BsCol2Inv: case Kind::BsUntangle: case Kind::FftJobs: case Kind::BsJobs: case Kind::JobReduce:
             for (int64_t q = 0; q < L.nitems; ++q)
                 if (b.offs[pr.items[L.item_off + q].desc].tmp == SIZE_MAX)
@@ -278,7 +278,7 @@ cjt_status run_program(const Program& pr, const ExecDesc* d_desc, const Item* d_
             break;
         case Kind::FftSingle:
         case Kind::FftPass1:
-        case Kind::FftPass1Inv:
+        case Kind::FftPass1Terms:
         case Kind::FftPass2:
         case Kind::JobRowReduce:
         case Kind::BsSingle:

@@ -83,6 +83,23 @@ struct Source<Src::FwdAsy> {
         const double v1 = c.y * x.y;
         return {in_range(n0, lo, hi) ? v0 : 0.0, in_range(n1, lo, hi) ? v1 : 0.0};
     }
+    // (C_{n,m} c_n) at n = 2t, 2t+1 for every block at once (degrees above N
+    // hold a stand-in that every block's mask clears)
+    __device__ static cx<double> term(const ExecDesc& d, int m, int t)
+    {
+        const int N = (int)d.N;
+        const int n0 = 2 * t, c0 = min(n0, N - 1);
+        const double* Cm = d.C + (int64_t)m * (d.N + 1);
+        const dpair8 c = ldg_pair(Cm + c0), x = ldg_pair(d.in + c0);
+        return {n0 == c0 ? c.x * x.x : c.y * x.y, c.y * x.y};
+    }
+    // block k keeps its degrees [deg_lo, deg_hi)
+    template <typename T>
+    __device__ static cx<T> keep(const ExecDesc& d, int k, int t, cx<T> z)
+    {
+        const int lo = (int)d.deg_lo[k], hi = (int)d.deg_hi[k];
+        return {in_range(2 * t, lo, hi) ? z.re : (T)0, in_range(2 * t + 1, lo, hi) ? z.im : (T)0};
+    }
 };
 
 template <>
@@ -118,6 +135,17 @@ struct Source<Src::InvAsy> {
         const int j0 = upper ? jl + 1 : jl, j1 = upper ? jl : jl + 1;
         const double r0 = upper ? a1 : a0, r1 = upper ? a0 : a1;
         return {in_range(j0, lo, hi) ? r0 : 0.0, in_range(j1, lo, hi) ? r1 : 0.0};
+    }
+    // the pair on block 0's window, which holds every other block's window
+    __device__ static cx<double> term(const ExecDesc& d, int m, int t) { return pair(d, 0, m, t); }
+    // block k keeps the points of its own window
+    template <typename T>
+    __device__ static cx<T> keep(const ExecDesc& d, int k, int t, cx<T> z)
+    {
+        const int lo = (int)d.win_lo[k], hi = (int)d.win_hi[k] + 1;
+        const int G = (int)d.G, q = 2 * t;
+        const int j0 = q <= G ? q : 2 * G - q, j1 = q + 1 <= G ? q + 1 : 2 * G - q - 1;
+        return {in_range(j0, lo, hi) ? z.re : (T)0, in_range(j1, lo, hi) ? z.im : (T)0};
     }
 };
 
@@ -447,13 +475,14 @@ __global__ void __launch_bounds__(128) k_pass1(const ExecDesc* __restrict__ desc
         [&](int t) { return to_t<T>(Source<S>::load(d, job, t)); }, [&](int i, cx<T> v) { stg(out + i, v); });
 }
 
-// Column pass of the inverse Hahn blocks, item (desc, term m, column tile).
-// The inputs of term m on block 0's window (which holds every other block's
-// window) are gathered once into registers; each block k then clears what
-// lies outside its own window, transforms, and writes tmp[k M + m].  This
-// reads g and (u_m, v_m) once per term instead of once per (block, term).
-template <typename T>
-__global__ void __launch_bounds__(128) k_pass1_inv(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
+// Column pass of every Hahn block of one term, item (desc, term m, column
+// tile).  The inputs of term m (forward: C_{n,m} c_n; inverse: the pair on
+// block 0's window, which holds every other block's window) are gathered
+// once into registers; each block k then clears what lies outside its own
+// degrees (forward) or window (inverse), transforms, and writes tmp[k M + m].
+// This reads the inputs once per term instead of once per (block, term).
+template <typename T, Src S>
+__global__ void __launch_bounds__(128) k_pass1_terms(const ExecDesc* __restrict__ descs, const Item* __restrict__ items)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
@@ -461,7 +490,6 @@ __global__ void __launch_bounds__(128) k_pass1_inv(const ExecDesc* __restrict__ 
     const ExecDesc& d = descs[it.desc];
     const FftGeom& g = geom_of<T>(d);
     const int m = it.a;
-    const int G = (int)d.G;
     const int lg1 = g.logL1, lg2 = g.logL2;
     const int F1 = 1 << lg1, F = 1 << (lg1 + lg2);
     const int ltc = lg1 >= 11 ? 0 : 11 - lg1;  // TC = 2048 / F1 columns
@@ -473,18 +501,13 @@ __global__ void __launch_bounds__(128) k_pass1_inv(const ExecDesc* __restrict__ 
     const cx<T>* tw1 = reinterpret_cast<const cx<T>*>(g.tw1);
     cx<T> z[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) z[r] = to_t<T>(Source<Src::InvAsy>::pair(d, 0, m, ((lt + r * step) << lg2) + col));
+    for (int r = 0; r < 16; ++r) z[r] = to_t<T>(Source<S>::term(d, m, ((lt + r * step) << lg2) + col));
     for (int k = 0; k < d.nblk; ++k) {
         // indices and addresses are recomputed per block: z alone stays live
         const int ltk = opaque(lt), colk = opaque(col);
-        const int lo = (int)d.win_lo[k], hi = (int)d.win_hi[k] + 1;
         cx<T> v[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int q = 2 * (((ltk + r * step) << lg2) + colk);
-            const int j0 = q <= G ? q : 2 * G - q, j1 = q + 1 <= G ? q + 1 : 2 * G - q - 1;
-            v[r] = {in_range(j0, lo, hi) ? z[r].re : (T)0, in_range(j1, lo, hi) ? z[r].im : (T)0};
-        }
+        for (int r = 0; r < 16; ++r) v[r] = Source<S>::template keep<T>(d, k, ((ltk + r * step) << lg2) + colk, z[r]);
         fft_reg<T>(v, lds + c * slice_stride(F1), lg1, ltk, true, tw1, 2 * F1);
         // column twiddles after the transform, so they hold no registers across it
         ColTw<T> ct;
@@ -1011,9 +1034,9 @@ cjt_status run(const Launch& L, const ExecDesc* dd, const Item* it, hipStream_t 
     switch (L.kind) {
     case Kind::FftSingle: return go(k_single<T, S, K>, L, s, dd, it, L.acc_off);
     case Kind::FftPass1: return go(k_pass1<T, S>, L, s, dd, it);
-    case Kind::FftPass1Inv:
-        if constexpr (S == Src::InvAsy) return go(k_pass1_inv<T>, L, s, dd, it);
-        return fail(CJT_EINVAL, "multi-block column pass is for the inverse Hahn blocks");
+    case Kind::FftPass1Terms:
+        if constexpr (S == Src::InvAsy || S == Src::FwdAsy) return go(k_pass1_terms<T, S>, L, s, dd, it);
+        return fail(CJT_EINVAL, "multi-block column pass is for the Hahn blocks");
     case Kind::FftPass2: return go(k_pass2<T, K, kMulti>, L, s, dd, it, L.acc_off);
     case Kind::JobRowReduce:
         if constexpr (kMulti) return go(k_job_row_reduce<T, K>, L, s, dd, it);
@@ -1122,13 +1145,12 @@ cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sin
             const int TC = g.L1 >= 2048 ? 1 : 2048 / g.L1;
             const int TU = g.L2 >= 1024 ? 1 : 1024 / g.L2;
             const int nth2 = 2 * TU * (g.L2 / 16);
-            const bool inv = src == Src::InvAsy;
-            Bucket& b1 = bucket(inv ? Kind::FftPass1Inv : Kind::FftPass1, 128, name_cols);
+            Bucket& b1 = bucket(multi ? Kind::FftPass1Terms : Kind::FftPass1, 128, name_cols);
             for (int t = 0; t < g.L2 / TC; ++t) {
-                if (inv) {  // one item per term: all blocks of the term in the workgroup
+                if (multi) {  // one item per term: all blocks of the term in the workgroup
                     for (int m = 0; m < d.M; ++m) b1.items.push_back(Item{i, m, t, 0});
                 } else {
-                    for (int it = 0; it < jobs; ++it) b1.items.push_back(Item{i, job_at(d, it, multi), t, 0});
+                    b1.items.push_back(Item{i, 0, t, 0});
                 }
             }
             b1.lds = std::max(b1.lds, (size_t)TC * slice_stride(g.L1) * esz);
@@ -1201,7 +1223,7 @@ cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sin
     };
     // launch order: single-workgroup kinds, then the two-pass chains in dependency order
     const Kind order[] = {Kind::FftSingle, Kind::BsSingle, Kind::FftJobs, Kind::BsJobs,  Kind::JobReduce,
-                          Kind::FftPass1,  Kind::FftPass1Inv, Kind::FftPass2, Kind::JobRowReduce, Kind::BsCol1,
+                          Kind::FftPass1,  Kind::FftPass1Terms, Kind::FftPass2, Kind::JobRowReduce, Kind::BsCol1,
                           Kind::BsRowConv, Kind::BsCol2Inv, Kind::BsUntangle};
     for (Kind k : order) {
         for (auto& b : bk) {

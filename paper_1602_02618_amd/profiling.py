@@ -28,7 +28,7 @@ KERNEL_SOURCES = ("csrc/rdft.hip", "csrc/fft_lds.h", "csrc/cjt_internal.h")
 COPY_BYTES = 256 << 20
 RECORD_TAG = "traffic-record:"
 # the kernel the roofline is quoted on: the inverse Hahn-block column pass
-DOMINANT = "k_pass1_inv<double>"
+DOMINANT = "k_pass1_terms<double,(Src)1>"
 
 
 def source_digest():
