@@ -1145,12 +1145,16 @@ cjt_status add_fft(Program& pr, const std::vector<int>& which, Src src, Sink sin
             const int TC = g.L1 >= 2048 ? 1 : 2048 / g.L1;
             const int TU = g.L2 >= 1024 ? 1 : 1024 / g.L2;
             const int nth2 = 2 * TU * (g.L2 / 16);
-            Bucket& b1 = bucket(multi ? Kind::FftPass1Terms : Kind::FftPass1, 128, name_cols);
+            // one item per term (all blocks of the term in the workgroup), except
+            // for forward calls with few instances, where one item per (block,
+            // term) gives a single long transform K times the workgroups
+            const bool terms = multi && (src == Src::InvAsy || !job_parallel);
+            Bucket& b1 = bucket(terms ? Kind::FftPass1Terms : Kind::FftPass1, 128, name_cols);
             for (int t = 0; t < g.L2 / TC; ++t) {
-                if (multi) {  // one item per term: all blocks of the term in the workgroup
+                if (terms) {
                     for (int m = 0; m < d.M; ++m) b1.items.push_back(Item{i, m, t, 0});
                 } else {
-                    b1.items.push_back(Item{i, 0, t, 0});
+                    for (int it = 0; it < jobs; ++it) b1.items.push_back(Item{i, job_at(d, it, multi), t, 0});
                 }
             }
             b1.lds = std::max(b1.lds, (size_t)TC * slice_stride(g.L1) * esz);
