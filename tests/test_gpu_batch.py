@@ -140,7 +140,7 @@ def test_job_parallel_and_fused_agree(lib):
     lengths)."""
     import torch
     rng = np.random.default_rng(24)
-    Ns = [8192, 1000, 5000, 16384, 300] + list(rng.integers(64, 3000, 65))
+    Ns = [8192, 1000, 5000, 16384, 65536, 300] + list(rng.integers(64, 3000, 64))
     plans = [lib.cjt_plan(int(N), *rng.uniform(-0.5, 0.5, 2), 0, lib.CJT_BATCH_INVARIANT) for N in Ns]
     cs = [rng.standard_normal(int(N) + 1) / (np.arange(int(N) + 1) + 1.0) for N in Ns]
     offs = np.concatenate([[0], np.cumsum([int(N) + 1 for N in Ns])]).astype(np.int64)
@@ -149,6 +149,6 @@ def test_job_parallel_and_fused_agree(lib):
         y = torch.empty_like(x)
         fn(plans, offs, x, y)
         yb = y.cpu().numpy()
-        for i in range(5):
+        for i in range(6):
             ys = single(plans[i], torch.as_tensor(cs[i], device="cuda")).cpu().numpy()
             assert np.array_equal(yb[offs[i]:offs[i + 1]], ys), (fn.__name__, i, Ns[i])
