@@ -208,8 +208,12 @@ void choose_partitions(int64_t N, double a, double b, int M, Part* f, Part* inv)
         compute_partition(2 * N, N, a, b, M, inv);
         return;
     }
+    // the model falls with M (fewer recurrence entries) until the Hahn-block
+    // transforms dominate and then rises; the sweep stops three terms past the
+    // last improvement (the first minimiser, as in a full sweep over 5..20)
     double best = INFINITY;
-    for (int m = 5; m <= 20; ++m) {
+    int since = 0;
+    for (int m = 5; m <= 20 && since < 3; ++m) {
         Part pf, pi;
         compute_partition(N, N, a, b, m, &pf);
         compute_partition(2 * N, N, a, b, m, &pi);
@@ -218,6 +222,9 @@ void choose_partitions(int64_t N, double a, double b, int M, Part* f, Part* inv)
             best = c;
             *f = pf;
             *inv = pi;
+            since = 0;
+        } else {
+            ++since;
         }
     }
 }
