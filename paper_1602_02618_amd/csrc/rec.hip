@@ -138,7 +138,7 @@ constexpr int kRec = 6 * 64 * kPPT;  // doubles per segment record (6 per point)
 // Segments compute their maps in parallel (two extra homogeneous chains),
 // and a short serial pass per point chains them.
 
-__host__ __device__ __forceinline__ int seg_count(int cut, int S) { return cut > 2 * S ? (cut + S - 1) / S : 1; }
+__host__ __device__ __forceinline__ int seg_count(int cut, int S) { return cut > S ? (cut + S - 1) / S : 1; }
 
 __host__ __device__ __forceinline__ int seg_len(int cut, int nseg)
 {
