@@ -97,7 +97,7 @@ def summarize_pmc(fetch_csv, write_csv, out_md, fetch_cmd, write_cmd):
     fscale = COPY_BYTES / (cf[1] * 1024.0)
     wscale = COPY_BYTES / (cw[1] * 1024.0)
     lines = ["# HBM traffic per dispatch (rocprofv3 FETCH_SIZE / WRITE_SIZE)", "",
-             "Commands (repository root on the GPU box, one counter per run):", "",
+             "Commands (from the repository root, one counter per run):", "",
              "```", fetch_cmd, write_cmd, "```", "",
              f"Calibration: the {COPY_BYTES >> 20} MiB device copy `{cf[0]}` reads as "
              f"{cf[1] / 1024:.1f} MiB FETCH_SIZE and writes as {cw[1] / 1024:.1f} MiB WRITE_SIZE, "
