@@ -499,19 +499,49 @@ __global__ void __launch_bounds__(64) k_rec_inv_init(const ExecDesc* __restrict_
     const TaskView tk = task_of(d, it.a);
     const int nseg = it.b;
     constexpr int R = 64 * kPPT;
+    // The records hold maps (0..3) and start states (4, 5) in disjoint
+    // slots, but the compiler cannot see that: a load placed after a store
+    // waits for it.  So each segment's maps are loaded one step ahead, before
+    // the current states are stored, and the lane's points (independent
+    // chains) step together.
+    double x[kPPT], y[kPPT], a[kPPT], b[kPPT], c[kPPT], e[kPPT];
+#pragma unroll
     for (int q = 0; q < kPPT; ++q) {
         const int idx = threadIdx.x + 64 * q;
-        double x = idx < tk.np ? ldg(d.p + tk.p0 + idx) : 0.0, y = 0.0;
-        for (int s = 0; s < nseg; ++s) {
-            double* rec = d.seg + (int64_t)(it.c + s) * kRec + idx;
-            stg(rec + 4 * R, x);
-            stg(rec + 5 * R, y);
-            if (s + 1 < nseg) {
-                const double nx = fma(ldg(rec), x, ldg(rec + 2 * R) * y);
-                const double ny = fma(ldg(rec + R), x, ldg(rec + 3 * R) * y);
-                x = nx;
-                y = ny;
-            }
+        x[q] = idx < tk.np ? ldg(d.p + tk.p0 + idx) : 0.0;
+        y[q] = 0.0;
+        const double* r = d.seg + (int64_t)it.c * kRec + idx;
+        a[q] = ldg(r);
+        b[q] = ldg(r + R);
+        c[q] = ldg(r + 2 * R);
+        e[q] = ldg(r + 3 * R);
+    }
+    for (int s = 0; s < nseg; ++s) {
+        double* rec = d.seg + (int64_t)(it.c + s) * kRec + threadIdx.x;
+        const bool more = s + 1 < nseg;
+        double na[kPPT], nb[kPPT], nc[kPPT], ne[kPPT];
+#pragma unroll
+        for (int q = 0; q < kPPT; ++q) {
+            // the next segment's maps (record s + 1 exists while s + 1 < nseg;
+            // the last step re-reads this record's maps, unused)
+            const double* r = rec + (more ? kRec : 0) + 64 * q;
+            na[q] = ldg(r);
+            nb[q] = ldg(r + R);
+            nc[q] = ldg(r + 2 * R);
+            ne[q] = ldg(r + 3 * R);
+        }
+#pragma unroll
+        for (int q = 0; q < kPPT; ++q) {
+            stg(rec + 64 * q + 4 * R, x[q]);
+            stg(rec + 64 * q + 5 * R, y[q]);
+            const double nx = fma(a[q], x[q], c[q] * y[q]);
+            const double ny = fma(b[q], x[q], e[q] * y[q]);
+            x[q] = nx;
+            y[q] = ny;
+            a[q] = na[q];
+            b[q] = nb[q];
+            c[q] = nc[q];
+            e[q] = ne[q];
         }
     }
 }
