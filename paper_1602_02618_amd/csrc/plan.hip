@@ -21,16 +21,34 @@ namespace {
 
 // log g_M(theta_i), theta_i = pi i / G: the envelope of |f_M| (Sec. 2.2),
 // summed in log space; -inf when every coefficient vanishes (a = b = 1/2).
-double log_gM(double th2, int M, const double* ca, const double* cb, double a, double b)
+// log of the coefficients a_l b_{M-l} of g_M's terms (-inf for zero terms):
+// independent of the angle, so computed once per (M, alpha, beta)
+struct GmCoef {
+    double lc[kMaxM + 2];
+    int M;
+};
+
+GmCoef gm_coef(int M, const double* ca, const double* cb)
 {
+    GmCoef g;
+    g.M = M;
+    for (int l = 0; l <= M; ++l) {
+        const double coef = ca[l] * cb[M - l];
+        g.lc[l] = coef > 0.0 ? log(coef) : -INFINITY;
+    }
+    return g;
+}
+
+double log_gM(double th2, const GmCoef& g, double a, double b)
+{
+    const int M = g.M;
     const double ls = log(sin(th2)), lc = log(cos(th2));
     double t[kMaxM + 2];
     int nt = 0;
     double mx = -INFINITY;
     for (int l = 0; l <= M; ++l) {
-        const double coef = ca[l] * cb[M - l];
-        if (!(coef > 0.0)) continue;
-        t[nt] = log(coef) + (l - M - b - 0.5) * lc - (l + a + 0.5) * ls;
+        if (g.lc[l] == -INFINITY) continue;
+        t[nt] = g.lc[l] + (l - M - b - 0.5) * lc - (l + a + 0.5) * ls;
         mx = fmax(mx, t[nt]);
         ++nt;
     }
@@ -39,6 +57,7 @@ double log_gM(double th2, int M, const double* ca, const double* cb, double a, d
     for (int q = 0; q < nt; ++q) s += exp(t[q] - mx);
     return mx + log(s);
 }
+
 
 }  // namespace
 
@@ -50,9 +69,10 @@ void compute_partition(int64_t G, int64_t cap, double a, double b, int M, Part* 
     P->M = M;
     double ca[kMaxM + 2], cb[kMaxM + 2];
     hahn_pochhammer(M, a, b, ca, cb);
-    auto lg = [&](int64_t i) { return log_gM(kPi * (double)i / (2.0 * (double)G), M, ca, cb, a, b); };
+    const GmCoef gc = gm_coef(M, ca, cb);
+    auto lg = [&](int64_t i) { return log_gM(kPi * (double)i / (2.0 * (double)G), gc, a, b); };
     const double leps = log(kEps);
-    const double lg_half = log_gM(kPi / 4.0, M, ca, cb, a, b);  // g_M(pi/2)
+    const double lg_half = log_gM(kPi / 4.0, gc, a, b);  // g_M(pi/2)
     const int64_t ncap1 = cap + 1;
     P->rec_entries = (G + 1) * ncap1;
     if (lg_half == -INFINITY) {
